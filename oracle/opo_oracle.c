@@ -1,0 +1,334 @@
+/*
+ * opo_oracle.c -- plain, slow, FP64 CPU reference of the optical parametric
+ * oscillator hot path: fixed-step symmetrized split-step Fourier (SSFM)
+ * propagation of the three-wave coupled-wave equations through a chi(2)
+ * crystal, repeated over cavity round trips.
+ *
+ * TEST INFRASTRUCTURE. Only the test suite, the smoke check and the CPU
+ * baseline of the benchmark load this file. It shares no code, header, table
+ * or constant with the GPU library and must never be linked into it.
+ *
+ * Sources (arXiv 2410.02532, "CUDA-based optical parametric oscillator
+ * simulator"):
+ *   Eqs. 2-4   coupled-wave equations                       -> cwe_rhs
+ *   Sec. 2.1   kappa_x = 2 pi d_eff / (n_x lambda_x)        -> ora_kappa
+ *   Eq. 5      linear operator (loss, GVM, GVD, TOD)        -> ora_dispersion
+ *   Sec. 2.2   RK4 for the nonlinear part, Eq. 10/11 split  -> ora_rk4, ora_pass
+ *   Eq. 9      unsymmetrized split (negative control only)  -> ora_pass_unsym
+ *   Eq. 6      resonant-field boundary condition            -> ora_roundtrips
+ *   Sec. 2.3   intracavity GDD and EOM                      -> ora_gdd, ora_eom
+ *   Sec. 4.1   main loop: pump read, pass, GDD, phase, EOM  -> ora_roundtrips
+ *
+ * Readings of passages the paper leaves open (each one is also recorded in
+ * the design notes):
+ *   - Fourier convention: forward X_k = sum_j x_j e^{-2 pi i jk/N} (not
+ *     normalized), inverse with e^{+...} and 1/N. Angular frequency of bin k
+ *     is 2 pi k/T for k < N/2 and 2 pi (k-N)/T otherwise (Nyquist negative).
+ *   - Eq. 5 is taken in the physically derived form (group-velocity term with
+ *     the sign that moves a slower field to later times, third-order term
+ *     beta3/6 d^3/dtau^3 without the printed i and 1/3):
+ *       H_x(w) = exp{ [ -alpha_x/2 + i(-db1_x w + b2_x w^2/2 - b3_x w^3/6) ] dz }
+ *     with db1_x = 1/v_x - 1/v_s (signal co-moving frame).
+ *   - RK4 advances the three fields together (classical coupled RK4) and
+ *     evaluates e^{+-i dk z} at the stage positions z0, z0+h/2, z0+h; the
+ *     first half-step of step j covers [z_j, z_j + dz/2], the second
+ *     [z_j + dz/2, z_j + dz]. Adjacent half-steps are not merged.
+ *   - Round trip: at its start a non-resonant pump is re-read from the input
+ *     pump and non-resonant signal/idler start at zero; after the pass the
+ *     energies sum_j |A_x(t_j)|^2 are recorded, then GDD, then
+ *     sqrt(R_x) e^{i delta_x} on resonant fields, then the EOM phase.
+ *
+ * Units: t [ps], z [mm], omega [rad/ps], lambda [um], d_eff [pm/V],
+ * dk [1/mm], alpha [1/mm], db1 [ps/mm], b2 [fs^2/mm], b3 [fs^3/mm],
+ * GDD [fs^2], f_pm [THz], fields A [V/m]. kappa is returned in
+ * 1/(mm V/m) so that kappa*A is in 1/mm.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+#define ORA_PI 3.14159265358979323846
+
+typedef struct {
+    int nt;                /* time points, a power of two                 */
+    double t_window_ps;    /* T: time window = round-trip time slice        */
+    double length_mm;      /* crystal length L                              */
+    double lambda_um[3];   /* pump, signal, idler wavelengths               */
+    double n[3];           /* refractive indices                            */
+    double deff_pm_per_v;  /* effective nonlinear coefficient               */
+    double dk_per_mm;      /* phase mismatch dk = k_p - k_s - k_i (Eq. 1)   */
+    double alpha_per_mm[3];
+    double db1_ps_per_mm[3];
+    double b2_fs2_per_mm[3];
+    double b3_fs3_per_mm[3];
+} ora_crystal;
+
+typedef struct {
+    int resonant[3];       /* which fields feel Eq. 6                       */
+    double refl[3];        /* R_x = 1 - theta_x                             */
+    double delta_rad[3];   /* detuning phase per round trip                 */
+    double gdd_fs2;        /* chirped-mirror GDD gamma                      */
+    int gdd_on[3];
+    double eom_beta;       /* EOM modulation depth                          */
+    double eom_fpm_thz;    /* EOM frequency                                 */
+    int eom_on[3];
+} ora_cavity;
+
+/* ---------------------------------------------------------------- FFT -- */
+
+/* Twiddles w_r = e^{-2 pi i r/N}, r < N/2, from cos/sin in double. */
+static cplx *twiddles(int n)
+{
+    int h = n / 2 > 0 ? n / 2 : 1;
+    cplx *w = malloc(sizeof(cplx) * (size_t)h);
+    for (int r = 0; r < h; r++) {
+        double a = 2.0 * ORA_PI * (double)r / (double)n;
+        w[r] = cos(a) - I * sin(a);
+    }
+    return w;
+}
+
+/* Iterative radix-2 decimation-in-time FFT with bit-reversal reordering.
+ * inverse = 0: X_k = sum_j x_j e^{-2 pi i jk/N};
+ * inverse = 1: x_j = (1/N) sum_k X_k e^{+2 pi i jk/N}. In place. */
+static void fft_with(cplx *x, int n, int inverse, const cplx *w)
+{
+    for (int i = 1, j = 0; i < n; i++) {
+        int bit = n >> 1;
+        for (; j & bit; bit >>= 1)
+            j ^= bit;
+        j ^= bit;
+        if (i < j) {
+            cplx t = x[i];
+            x[i] = x[j];
+            x[j] = t;
+        }
+    }
+    for (int len = 2; len <= n; len <<= 1) {
+        int half = len / 2, stride = n / len;
+        for (int base = 0; base < n; base += len) {
+            for (int k = 0; k < half; k++) {
+                cplx wk = inverse ? conj(w[k * stride]) : w[k * stride];
+                cplx u = x[base + k];
+                cplx v = x[base + k + half] * wk;
+                x[base + k] = u + v;
+                x[base + k + half] = u - v;
+            }
+        }
+    }
+    if (inverse)
+        for (int i = 0; i < n; i++)
+            x[i] /= (double)n;
+}
+
+void ora_fft(cplx *x, int n, int inverse)
+{
+    cplx *w = twiddles(n);
+    fft_with(x, n, inverse, w);
+    free(w);
+}
+
+/* ------------------------------------------------------ coefficients -- */
+
+/* Angular frequency of DFT bin k on a window of T ps (numpy fftfreq order). */
+double ora_omega(int k, int n, double t_window_ps)
+{
+    int ks = (k < n / 2) ? k : k - n;
+    return 2.0 * ORA_PI * (double)ks / t_window_ps;
+}
+
+/* Nonlinear coupling, Sec. 2.1: kappa_x = 2 pi d_eff / (n_x lambda_x).
+ * pm/V over um gives 1e-6 per metre; 1e-3 more converts to per mm. */
+void ora_kappa(const ora_crystal *c, double kappa[3])
+{
+    for (int x = 0; x < 3; x++)
+        kappa[x] = 2.0 * ORA_PI * c->deff_pm_per_v / (c->n[x] * c->lambda_um[x]) * 1e-9;
+}
+
+/* Frequency-domain propagator of Eq. 5 (reading above) over a step dz. */
+void ora_dispersion(const ora_crystal *c, int x, double dz, cplx *h)
+{
+    double b2 = c->b2_fs2_per_mm[x] * 1e-6; /* ps^2/mm */
+    double b3 = c->b3_fs3_per_mm[x] * 1e-9; /* ps^3/mm */
+    for (int k = 0; k < c->nt; k++) {
+        double w = ora_omega(k, c->nt, c->t_window_ps);
+        double phase = -c->db1_ps_per_mm[x] * w + 0.5 * b2 * w * w - b3 * w * w * w / 6.0;
+        h[k] = cexp((-0.5 * c->alpha_per_mm[x] + I * phase) * dz);
+    }
+}
+
+/* ------------------------------------------------------- nonlinear -- */
+
+/* Right-hand side of Eqs. 2-4 without the linear operator, at one time
+ * point; ph = e^{+i dk z}. */
+static void cwe_rhs(const double kap[3], cplx ph, cplx ap, cplx as, cplx ai, cplx out[3])
+{
+    out[0] = I * kap[0] * as * ai * conj(ph);
+    out[1] = I * kap[1] * ap * conj(ai) * ph;
+    out[2] = I * kap[2] * ap * conj(as) * ph;
+}
+
+/* One classical RK4 step of size h from z0 for all time points of the
+ * three fields stored as A[x*nt + j]. */
+void ora_rk4(const ora_crystal *c, cplx *a, double z0, double h)
+{
+    int n = c->nt;
+    double kap[3];
+    ora_kappa(c, kap);
+    cplx ph0 = cexp(I * c->dk_per_mm * z0);
+    cplx ph1 = cexp(I * c->dk_per_mm * (z0 + 0.5 * h));
+    cplx ph2 = cexp(I * c->dk_per_mm * (z0 + h));
+    for (int j = 0; j < n; j++) {
+        cplx y[3] = {a[j], a[n + j], a[2 * n + j]};
+        cplx k1[3], k2[3], k3[3], k4[3], t[3];
+        cwe_rhs(kap, ph0, y[0], y[1], y[2], k1);
+        for (int x = 0; x < 3; x++)
+            t[x] = y[x] + 0.5 * h * k1[x];
+        cwe_rhs(kap, ph1, t[0], t[1], t[2], k2);
+        for (int x = 0; x < 3; x++)
+            t[x] = y[x] + 0.5 * h * k2[x];
+        cwe_rhs(kap, ph1, t[0], t[1], t[2], k3);
+        for (int x = 0; x < 3; x++)
+            t[x] = y[x] + h * k3[x];
+        cwe_rhs(kap, ph2, t[0], t[1], t[2], k4);
+        for (int x = 0; x < 3; x++)
+            a[x * n + j] = y[x] + h / 6.0 * (k1[x] + 2.0 * k2[x] + 2.0 * k3[x] + k4[x]);
+    }
+}
+
+/* -------------------------------------------------------- linear -- */
+
+static void linear_with(cplx *field, int n, const cplx *h, const cplx *w)
+{
+    fft_with(field, n, 0, w);
+    for (int k = 0; k < n; k++)
+        field[k] *= h[k];
+    fft_with(field, n, 1, w);
+}
+
+/* e^{L_x dz} for the three fields: FFT, multiply by H_x, inverse FFT. */
+void ora_linear(const ora_crystal *c, cplx *a, double dz)
+{
+    int n = c->nt;
+    cplx *w = twiddles(n);
+    cplx *h = malloc(sizeof(cplx) * (size_t)n);
+    for (int x = 0; x < 3; x++) {
+        ora_dispersion(c, x, dz, h);
+        linear_with(a + (size_t)x * n, n, h, w);
+    }
+    free(h);
+    free(w);
+}
+
+/* ---------------------------------------------------------- SSFM -- */
+
+/* nz symmetrized steps (Eqs. 10-11): N(dz/2) -> F^-1 e^{L dz} F -> N(dz/2),
+ * step j starting at z0 + j dz. */
+void ora_pass(const ora_crystal *c, cplx *a, int nz, double dz, double z0)
+{
+    int n = c->nt;
+    cplx *w = twiddles(n);
+    cplx *h = malloc(sizeof(cplx) * (size_t)n * 3);
+    for (int x = 0; x < 3; x++)
+        ora_dispersion(c, x, dz, h + (size_t)x * n);
+    for (int j = 0; j < nz; j++) {
+        double zj = z0 + (double)j * dz;
+        ora_rk4(c, a, zj, 0.5 * dz);
+        for (int x = 0; x < 3; x++)
+            linear_with(a + (size_t)x * n, n, h + (size_t)x * n, w);
+        ora_rk4(c, a, zj + 0.5 * dz, 0.5 * dz);
+    }
+    free(h);
+    free(w);
+}
+
+/* Negative control: the unsymmetrized split of Eq. 9, e^{L dz} e^{N dz}
+ * (a full RK4 step, then the full linear step). Not part of the method. */
+void ora_pass_unsym(const ora_crystal *c, cplx *a, int nz, double dz, double z0)
+{
+    int n = c->nt;
+    cplx *w = twiddles(n);
+    cplx *h = malloc(sizeof(cplx) * (size_t)n * 3);
+    for (int x = 0; x < 3; x++)
+        ora_dispersion(c, x, dz, h + (size_t)x * n);
+    for (int j = 0; j < nz; j++) {
+        ora_rk4(c, a, z0 + (double)j * dz, dz);
+        for (int x = 0; x < 3; x++)
+            linear_with(a + (size_t)x * n, n, h + (size_t)x * n, w);
+    }
+    free(h);
+    free(w);
+}
+
+/* ---------------------------------------------- intracavity elements -- */
+
+/* Chirped-mirror GDD (Sec. 2.3): A~(w) -> A~(w) e^{i gamma w^2/2}. */
+void ora_gdd(cplx *field, int n, double t_window_ps, double gdd_fs2)
+{
+    double g = gdd_fs2 * 1e-6; /* ps^2 */
+    cplx *w = twiddles(n);
+    fft_with(field, n, 0, w);
+    for (int k = 0; k < n; k++) {
+        double om = ora_omega(k, n, t_window_ps);
+        field[k] *= cexp(I * 0.5 * g * om * om);
+    }
+    fft_with(field, n, 1, w);
+    free(w);
+}
+
+/* Electro-optic phase modulator (Sec. 2.3): A(t) -> A(t) e^{i beta sin(2 pi f t)},
+ * t_j = -T/2 + j T/N. */
+void ora_eom(cplx *field, int n, double t_window_ps, double beta, double fpm_thz)
+{
+    double dt = t_window_ps / (double)n;
+    for (int j = 0; j < n; j++) {
+        double t = -0.5 * t_window_ps + (double)j * dt;
+        field[j] *= cexp(I * beta * sin(2.0 * ORA_PI * fpm_thz * t));
+    }
+}
+
+/* ----------------------------------------------------- round trips -- */
+
+/* n_rt cavity round trips (Sec. 4.1 main loop with Eq. 6). energy[m*3+x]
+ * receives sum_j |A_x(t_j)|^2 after the crystal pass of round trip m.
+ * pump_in: nt input-pump samples read into a non-resonant pump at the
+ * start of every round trip. */
+void ora_roundtrips(const ora_crystal *c, const ora_cavity *cav, cplx *a,
+                    const cplx *pump_in, int nz, int n_rt, double *energy)
+{
+    int n = c->nt;
+    double dz = c->length_mm / (double)nz;
+    for (int m = 0; m < n_rt; m++) {
+        if (!cav->resonant[0])
+            memcpy(a, pump_in, sizeof(cplx) * (size_t)n);
+        for (int x = 1; x < 3; x++)
+            if (!cav->resonant[x])
+                memset(a + (size_t)x * n, 0, sizeof(cplx) * (size_t)n);
+
+        ora_pass(c, a, nz, dz, 0.0);
+
+        for (int x = 0; x < 3; x++) {
+            double e = 0.0;
+            for (int j = 0; j < n; j++) {
+                cplx v = a[(size_t)x * n + j];
+                e += creal(v) * creal(v) + cimag(v) * cimag(v);
+            }
+            energy[m * 3 + x] = e;
+        }
+        for (int x = 0; x < 3; x++)
+            if (cav->gdd_on[x] && cav->gdd_fs2 != 0.0)
+                ora_gdd(a + (size_t)x * n, n, c->t_window_ps, cav->gdd_fs2);
+        for (int x = 0; x < 3; x++)
+            if (cav->resonant[x]) {
+                cplx f = sqrt(cav->refl[x]) * cexp(I * cav->delta_rad[x]);
+                for (int j = 0; j < n; j++)
+                    a[(size_t)x * n + j] *= f;
+            }
+        for (int x = 0; x < 3; x++)
+            if (cav->eom_on[x] && cav->eom_beta != 0.0)
+                ora_eom(a + (size_t)x * n, n, c->t_window_ps, cav->eom_beta, cav->eom_fpm_thz);
+    }
+}

@@ -1,0 +1,207 @@
+"""ctypes front end of the FP64 C oracle (``opo_oracle.c``).
+
+Test infrastructure only. Every function takes and returns numpy complex128
+arrays; fields are stacked as ``a[x, j]`` with x = 0 pump, 1 signal, 2 idler.
+Parameters come as plain dicts (keys as in :class:`Crystal` / :class:`Cavity`).
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "opo_oracle.c")
+_LIB = os.path.join(_HERE, "libopo_oracle.so")
+
+_c3 = ctypes.c_double * 3
+_i3 = ctypes.c_int * 3
+
+
+class Crystal(ctypes.Structure):
+    _fields_ = [
+        ("nt", ctypes.c_int),
+        ("t_window_ps", ctypes.c_double),
+        ("length_mm", ctypes.c_double),
+        ("lambda_um", _c3),
+        ("n", _c3),
+        ("deff_pm_per_v", ctypes.c_double),
+        ("dk_per_mm", ctypes.c_double),
+        ("alpha_per_mm", _c3),
+        ("db1_ps_per_mm", _c3),
+        ("b2_fs2_per_mm", _c3),
+        ("b3_fs3_per_mm", _c3),
+    ]
+
+    @classmethod
+    def from_dict(cls, d):
+        c = cls()
+        for name, ctype in cls._fields_:
+            v = d[name]
+            if ctype in (_c3,):
+                setattr(c, name, _c3(*[float(x) for x in v]))
+            elif ctype is ctypes.c_int:
+                setattr(c, name, int(v))
+            else:
+                setattr(c, name, float(v))
+        return c
+
+
+class Cavity(ctypes.Structure):
+    _fields_ = [
+        ("resonant", _i3),
+        ("refl", _c3),
+        ("delta_rad", _c3),
+        ("gdd_fs2", ctypes.c_double),
+        ("gdd_on", _i3),
+        ("eom_beta", ctypes.c_double),
+        ("eom_fpm_thz", ctypes.c_double),
+        ("eom_on", _i3),
+    ]
+
+    @classmethod
+    def from_dict(cls, d):
+        c = cls()
+        for name, ctype in cls._fields_:
+            v = d[name]
+            if ctype is _i3:
+                setattr(c, name, _i3(*[int(x) for x in v]))
+            elif ctype is _c3:
+                setattr(c, name, _c3(*[float(x) for x in v]))
+            else:
+                setattr(c, name, float(v))
+        return c
+
+
+def build(force=False):
+    """Compile the oracle with gcc (strict IEEE: no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+                               "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        lib.ora_fft.argtypes = [P, ctypes.c_int, ctypes.c_int]
+        lib.ora_omega.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double]
+        lib.ora_omega.restype = ctypes.c_double
+        lib.ora_kappa.argtypes = [ctypes.POINTER(Crystal), P]
+        lib.ora_dispersion.argtypes = [ctypes.POINTER(Crystal), ctypes.c_int, ctypes.c_double, P]
+        lib.ora_rk4.argtypes = [ctypes.POINTER(Crystal), P, ctypes.c_double, ctypes.c_double]
+        lib.ora_linear.argtypes = [ctypes.POINTER(Crystal), P, ctypes.c_double]
+        lib.ora_pass.argtypes = [ctypes.POINTER(Crystal), P, ctypes.c_int, ctypes.c_double,
+                                 ctypes.c_double]
+        lib.ora_pass_unsym.argtypes = lib.ora_pass.argtypes
+        lib.ora_gdd.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        lib.ora_eom.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        lib.ora_roundtrips.argtypes = [ctypes.POINTER(Crystal), ctypes.POINTER(Cavity), P, P,
+                                       ctypes.c_int, ctypes.c_int, P]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _cplx(a):
+    return np.ascontiguousarray(a, dtype=np.complex128).copy()
+
+
+def _fields(a, nt):
+    a = _cplx(a)
+    if a.shape != (3, nt):
+        raise ValueError("fields must have shape (3, %d), got %s" % (nt, a.shape))
+    return a
+
+
+def fft(x):
+    """Unnormalized forward DFT, X_k = sum_j x_j e^{-2 pi i jk/N} (radix-2)."""
+    x = _cplx(x)
+    _load().ora_fft(_ptr(x), x.size, 0)
+    return x
+
+
+def ifft(x):
+    """Inverse DFT with the 1/N factor."""
+    x = _cplx(x)
+    _load().ora_fft(_ptr(x), x.size, 1)
+    return x
+
+
+def omega(n, t_window_ps):
+    lib = _load()
+    return np.array([lib.ora_omega(k, n, t_window_ps) for k in range(n)])
+
+
+def kappa(crystal):
+    out = np.zeros(3)
+    _load().ora_kappa(ctypes.byref(Crystal.from_dict(crystal)), _ptr(out))
+    return out
+
+
+def dispersion(crystal, field, dz):
+    h = np.zeros(crystal["nt"], dtype=np.complex128)
+    _load().ora_dispersion(ctypes.byref(Crystal.from_dict(crystal)), field, dz, _ptr(h))
+    return h
+
+
+def rk4(crystal, a, z0, h):
+    a = _fields(a, crystal["nt"])
+    _load().ora_rk4(ctypes.byref(Crystal.from_dict(crystal)), _ptr(a), z0, h)
+    return a
+
+
+def linear(crystal, a, dz):
+    a = _fields(a, crystal["nt"])
+    _load().ora_linear(ctypes.byref(Crystal.from_dict(crystal)), _ptr(a), dz)
+    return a
+
+
+def ssfm_pass(crystal, a, nz, dz, z0=0.0):
+    """nz symmetrized SSFM steps of size dz starting at z0; returns new fields."""
+    a = _fields(a, crystal["nt"])
+    _load().ora_pass(ctypes.byref(Crystal.from_dict(crystal)), _ptr(a), int(nz), float(dz),
+                     float(z0))
+    return a
+
+
+def ssfm_pass_unsym(crystal, a, nz, dz, z0=0.0):
+    a = _fields(a, crystal["nt"])
+    _load().ora_pass_unsym(ctypes.byref(Crystal.from_dict(crystal)), _ptr(a), int(nz),
+                           float(dz), float(z0))
+    return a
+
+
+def gdd(field, t_window_ps, gdd_fs2):
+    f = _cplx(field)
+    _load().ora_gdd(_ptr(f), f.size, t_window_ps, gdd_fs2)
+    return f
+
+
+def eom(field, t_window_ps, beta, fpm_thz):
+    f = _cplx(field)
+    _load().ora_eom(_ptr(f), f.size, t_window_ps, beta, fpm_thz)
+    return f
+
+
+def roundtrips(crystal, cavity, a, pump_in, nz, n_rt):
+    """n_rt cavity round trips. Returns (fields, energies[n_rt, 3])."""
+    nt = crystal["nt"]
+    a = _fields(a, nt)
+    p = _cplx(np.broadcast_to(np.asarray(pump_in, dtype=np.complex128), (nt,)))
+    e = np.zeros((int(n_rt), 3))
+    _load().ora_roundtrips(ctypes.byref(Crystal.from_dict(crystal)),
+                           ctypes.byref(Cavity.from_dict(cavity)), _ptr(a), _ptr(p),
+                           int(nz), int(n_rt), _ptr(e))
+    return a, e
