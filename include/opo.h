@@ -1,0 +1,178 @@
+/*
+ * opo.h -- C ABI of the MI355X (gfx950) optical parametric oscillator hot path.
+ *
+ * The library propagates the three-wave coupled-wave equations (Eqs. 2-4 of
+ * arXiv 2410.02532) for pump (p, index 0), signal (s, 1) and idler (i, 2)
+ * through a chi(2) crystal with the fixed-step symmetrized split-step Fourier
+ * method (Sec. 2.2, Eqs. 10-11: nonlinear half-step by RK4, linear step in
+ * the frequency domain, nonlinear half-step), and repeats the pass over cavity
+ * round trips with the resonant-field boundary condition of Eq. 6 and the
+ * intracavity elements of Sec. 2.3 (chirped-mirror GDD, electro-optic phase
+ * modulator), in the loop order of Sec. 4.1.
+ *
+ * Conventions shared by every call:
+ *   - Units: time ps, length mm, wavelength um, d_eff pm/V, dk 1/mm,
+ *     alpha 1/mm, group-delay mismatch ps/mm, GVD fs^2/mm, TOD fs^3/mm,
+ *     GDD fs^2, EOM frequency THz, phases rad, fields V/m.
+ *   - Grid (Sec. 2.4): nt samples t_j = -T/2 + j T/nt over a window T; nt is
+ *     a power of two. Frequency bin k has angular frequency 2 pi k/T for
+ *     k < nt/2 and 2 pi (k - nt)/T otherwise.
+ *   - Linear operator (Eq. 5, read in its physically derived form): over a
+ *     step dz the spectrum of field x is multiplied by
+ *     exp{[-alpha_x/2 + i(-db1_x w + b2_x w^2/2 - b3_x w^3/6)] dz}, db1_x being
+ *     the group-delay mismatch to the signal (a positive value is slower and
+ *     drifts to later t). The phase is formed and reduced modulo 2 pi in FP64.
+ *   - Coupling (Sec. 2.1): kappa_x = 2 pi d_eff/(n_x lambda_x).
+ *   - Host field arrays are interleaved complex128: re, im, re, im, ...
+ *   - Every call returns an opo_status; negative values are errors and
+ *     opo_last_error() returns a message for the calling thread. No C++
+ *     exception crosses the boundary. A handle must not be used from two
+ *     threads at once; distinct handles are independent.
+ */
+#ifndef OPO_H
+#define OPO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    OPO_OK = 0,
+    OPO_EINVAL = -1,     /* bad argument, size or physical parameter            */
+    OPO_ENOMEM = -2,     /* device or host allocation failed                    */
+    OPO_EDEVICE = -3,    /* no usable gfx950 device, or a HIP call failed       */
+    OPO_ENONFINITE = -4, /* a round-trip energy became NaN or Inf               */
+    OPO_ESTATE = -5      /* NULL or already destroyed handle, bad call order    */
+} opo_status;
+
+enum { OPO_F32 = 0, OPO_F64 = 1 };
+
+typedef struct opo_s opo_t;
+
+/* Fields and grid of one instance. */
+typedef struct {
+    int32_t nt;             /* time samples, power of two, 2 .. 2^20 (FP64: 2^19) */
+    double t_window_ps;     /* window T (> 0)                                     */
+    double lambda_um[3];    /* wavelengths p, s, i (> 0)                          */
+    double n[3];            /* refractive indices (> 0)                           */
+    const double *init;     /* 3*nt complex128 initial fields p, s, i (time
+                               domain), host memory, copied; NULL = all zero      */
+    const double *pump_in;  /* nt complex128 input pump read into a non-resonant
+                               pump at the start of every round trip; NULL = the
+                               constant pump_cw below                             */
+    double pump_cw[2];      /* constant input pump (re, im) when pump_in is NULL  */
+} opo_fields_t;
+
+/* Crystal: length, z-grid and the coefficients of Eqs. 2-5. */
+typedef struct {
+    double length_mm;       /* L (> 0)                                            */
+    int32_t nz;             /* steps per pass in cavity_roundtrip (>= 1); every
+                               instance of a batch must use the same nz           */
+    double deff_pm_per_v;   /* d_eff                                              */
+    double dk_per_mm;       /* phase mismatch dk = k_p - k_s - k_i (Eq. 1)        */
+    double alpha_per_mm[3]; /* field loss alpha_x (power attenuation)             */
+    double db1_ps_per_mm[3];/* 1/v_x - 1/v_s                                      */
+    double b2_fs2_per_mm[3];/* GVD k''_x                                          */
+    double b3_fs3_per_mm[3];/* TOD k'''_x                                         */
+} opo_crystal_t;
+
+/* Cavity: Eq. 6 and the Sec. 2.3 elements, applied after every pass. */
+typedef struct {
+    int32_t resonant[3];    /* 1 = field is fed back (Eq. 6); a non-resonant pump
+                               is re-read from the input, a non-resonant signal or
+                               idler restarts from zero                           */
+    double refl[3];         /* R_x = 1 - theta_x in [0, 1] (resonant fields)      */
+    double delta_rad[3];    /* detuning phase delta_x per round trip              */
+    double gdd_fs2;         /* chirped-mirror GDD gamma: spectrum * e^{i gamma w^2/2} */
+    int32_t gdd_on[3];      /* fields that receive the GDD                        */
+    double eom_beta;        /* EOM depth: A(t) * e^{i beta sin(2 pi f t)}         */
+    double eom_fpm_thz;     /* EOM frequency f                                    */
+    int32_t eom_on[3];      /* fields that pass the EOM                           */
+} opo_cavity_t;
+
+/* Run-time options. A zeroed struct (or NULL) selects the defaults. */
+typedef struct {
+    int32_t precision;      /* OPO_F32: complex64 fields, FFTs and RK4 with FP64
+                               phase arguments and energy sums (default);
+                               OPO_F64: complex128 throughout                     */
+    int32_t device;         /* HIP device ordinal (default 0)                     */
+    void *stream;           /* hipStream_t to run on; NULL = a stream the library
+                               creates (default priority)                         */
+    void *state;            /* optional device buffer of opo_state_bytes() bytes
+                               that holds the fields; owned by the caller and
+                               kept alive until opo_destroy; NULL = the library
+                               allocates it                                       */
+    uint64_t state_bytes;   /* size of *state                                     */
+    int32_t tile_a;         /* points per column-pass tile (0 = autotuned)        */
+    int32_t tile_b;         /* points per row-pass tile (0 = autotuned)           */
+    int32_t use_graph;      /* 1 = replay each round trip from a hipGraph
+                               (default), -1 = plain launches                     */
+} opo_options_t;
+
+/* Device bytes of field state for n instances (fields[i].nt) at a precision. */
+uint64_t opo_state_bytes(int32_t n, const opo_fields_t *fields, int32_t precision);
+
+/* Create a handle for one OPO instance: validates every parameter (nt a power
+ * of two in range, finite positive physical constants, R in [0, 1], and the
+ * step criterion of Sec. 2.4, kappa_x |A|max dz < 0.5 for dz = L/nz), copies the
+ * host inputs to the device and builds the FFT and coupling tables. On error
+ * *h is NULL. */
+int opo_init(opo_t **h, const opo_fields_t *fields, const opo_crystal_t *crystal,
+             const opo_cavity_t *cavity, const opo_options_t *options);
+
+/* Same for n independent instances (arrays of n structs; nt may differ) that
+ * advance together in every launch. */
+int opo_init_batch(opo_t **h, int32_t n, const opo_fields_t *fields,
+                   const opo_crystal_t *crystals, const opo_cavity_t *cavities,
+                   const opo_options_t *options);
+
+/* One crystal pass of nz symmetrized SSFM steps of size dz [mm] (Eq. 11) for
+ * every instance, continuing z from the end of the previous call (so two calls
+ * of nz/2 equal one of nz). No cavity operation. Asynchronous on the handle's
+ * stream; opo_sync waits. */
+int ssfm_propagate(opo_t *h, int32_t nz, double dz);
+
+/* n_rt cavity round trips (Sec. 4.1): read the input pump into a non-resonant
+ * pump and zero non-resonant signal/idler, one pass of crystal.nz steps with
+ * dz = L/nz from z = 0, record sum_j |A_x(t_j)|^2 in FP64, apply GDD, the
+ * mirror factor sqrt(R_x) e^{i delta_x} of Eq. 6, then the EOM. Appends n_rt
+ * rows to the energy history. Returns OPO_ENONFINITE (after finishing the
+ * call) if any recorded energy is not finite; opo_history_length and the
+ * history tell where. Synchronizes the stream at the end. */
+int cavity_roundtrip(opo_t *h, int32_t n_rt);
+
+/* Wait for all work queued on the handle's stream. */
+int opo_sync(opo_t *h);
+
+/* Copy field `field` (0 p, 1 s, 2 i) of instance `inst` to/from host memory
+ * as nt interleaved complex128 values. domain 0 = time samples A(t_j);
+ * domain 1 (get only) = unnormalized DFT sum_j A(t_j) e^{-2 pi i jk/nt} in
+ * natural bin order. set also resets the instance's z to 0. */
+int opo_get_fields(opo_t *h, int32_t inst, int32_t field, int32_t domain, double *out);
+int opo_set_fields(opo_t *h, int32_t inst, int32_t field, const double *in);
+
+/* Energy history: out receives min(capacity, rows) rows of 3 doubles
+ * sum_j |A_x(t_j)|^2 (p, s, i) after each pass of cavity_roundtrip, oldest
+ * first; *rows receives the number recorded so far. */
+int opo_get_energy_history(opo_t *h, int32_t inst, double *out, int32_t capacity,
+                           int32_t *rows);
+
+/* Time samples t_j [ps] and angular frequencies w_k [rad/ps] of an instance. */
+int opo_get_grid(opo_t *h, int32_t inst, double *t, double *omega);
+
+/* Number of instances, and the current z [mm] of the handle. */
+int opo_info(opo_t *h, int32_t *n_instances, double *z_mm);
+
+/* Release all device memory the library allocated, and the handle. */
+int opo_destroy(opo_t *h);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *opo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OPO_H */

@@ -1,0 +1,771 @@
+// opo.hip -- host side of the C ABI declared in include/opo.h: validation,
+// planning (four-step split, tile shapes, FP64 tables), launch sequences of a
+// crystal pass and of a cavity round trip, hipGraph replay, read-back.
+#include "opo.h"
+#include "ssfm_kernels.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+namespace opo {
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                            \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return fail(OPO_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+    } while (0)
+
+static constexpr int kHistChunk = 1024;   // round trips buffered on the device per read-back
+static constexpr double kTwoPi = 6.283185307179586476925286766559;
+static constexpr double kPi = 3.1415926535897932384626433832795;
+
+struct Plan {
+    int log2n1, log2n2, log2cols, log2rows;
+};
+
+static int ilog2(long long v)
+{
+    int l = 0;
+    while ((1LL << l) < v) ++l;
+    return l;
+}
+
+// Default tile sizes (points per tile) before any autotuning.
+static int default_tile_a(int precision) { return precision == OPO_F64 ? 768 : 1536; }
+static int default_tile_b(int precision) { return precision == OPO_F64 ? 512 : 1024; }
+
+static Plan make_plan(int nt, int precision, int tile_a, int tile_b)
+{
+    Plan p;
+    const int l = ilog2(nt);
+    p.log2n2 = std::min(l / 2, 8);
+    p.log2n1 = l - p.log2n2;
+    const int maxpts = kThreads * (precision == OPO_F64 ? max_pts<double>() : max_pts<float>());
+    // columns per column tile: 3 * cols * n2 points, within [1, n1]
+    int ca = std::max(1, std::min(tile_a, maxpts) / (3 << p.log2n2));
+    int lc = 0;
+    while ((2 << lc) <= ca) ++lc;
+    p.log2cols = std::min(lc, p.log2n1);
+    while (p.log2cols > 0 && (3 << (p.log2n2 + p.log2cols)) > maxpts) --p.log2cols;
+    int rb = std::max(1, std::min(tile_b, maxpts) >> p.log2n1);
+    int lr = 0;
+    while ((2 << lr) <= rb) ++lr;
+    p.log2rows = std::min(lr, p.log2n2);
+    return p;
+}
+
+} // namespace opo
+
+using namespace opo;
+
+struct opo_s {
+    int precision = OPO_F32;
+    int device = 0;
+    int n_inst = 0;
+    int nz = 1;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void *state = nullptr;
+    bool own_state = false;
+    size_t state_bytes = 0;
+    size_t elem = 8;                 // bytes per complex sample
+    void *pump = nullptr;            // input-pump samples (pulsed pumps only)
+    std::vector<InstDesc> inst;
+    InstDesc *d_inst = nullptr;
+    int tiles_a = 0, tiles_b = 0;
+    int *d_tile_a = nullptr, *d_tile_b = nullptr;
+    void *d_tw = nullptr, *d_tw4 = nullptr;
+    double *d_partial = nullptr;
+    double *d_hist = nullptr;
+    int *d_counter = nullptr;
+    size_t lds_a = 0, lds_b = 0;
+    double z = 0.0;
+    std::vector<double> hist;        // [rows][n_inst][3]
+    int hist_rows = 0;
+    bool any_gdd = false, any_eom = false;
+    int use_graph = 1;
+    hipGraphExec_t graph = nullptr;
+    void *scratch = nullptr;         // spectrum read-out
+    std::vector<double> t_window;    // T of every instance [ps]
+};
+
+namespace opo {
+
+// Live handles, so that a NULL, foreign or destroyed handle is reported as
+// OPO_ESTATE instead of being dereferenced.
+static std::mutex g_live_mu;
+static std::unordered_set<const opo_t *> g_live;
+
+static bool is_live(const opo_t *h)
+{
+    std::lock_guard<std::mutex> lk(g_live_mu);
+    return h && g_live.count(h) != 0;
+}
+
+static bool finite3(const double *v)
+{
+    return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
+}
+
+static int validate(int n, const opo_fields_t *f, const opo_crystal_t *c, const opo_cavity_t *k,
+                    int precision)
+{
+    const int max_log2 = precision == OPO_F64 ? 19 : 20;
+    for (int i = 0; i < n; ++i) {
+        const std::string at = "instance " + std::to_string(i) + ": ";
+        const int nt = f[i].nt;
+        if (nt < 2 || (nt & (nt - 1)) || ilog2(nt) > max_log2)
+            return fail(OPO_EINVAL, at + "nt must be a power of two in [2, 2^" +
+                                        std::to_string(max_log2) + "]");
+        if (!(f[i].t_window_ps > 0.0) || !std::isfinite(f[i].t_window_ps))
+            return fail(OPO_EINVAL, at + "t_window_ps must be finite and > 0");
+        for (int x = 0; x < 3; ++x)
+            if (!(f[i].lambda_um[x] > 0.0) || !std::isfinite(f[i].lambda_um[x]) ||
+                !(f[i].n[x] > 0.0) || !std::isfinite(f[i].n[x]))
+                return fail(OPO_EINVAL, at + "wavelengths and indices must be finite and > 0");
+        if (!std::isfinite(f[i].pump_cw[0]) || !std::isfinite(f[i].pump_cw[1]))
+            return fail(OPO_EINVAL, at + "pump_cw must be finite");
+        if (!(c[i].length_mm > 0.0) || !std::isfinite(c[i].length_mm))
+            return fail(OPO_EINVAL, at + "length_mm must be finite and > 0");
+        if (c[i].nz < 1) return fail(OPO_EINVAL, at + "nz must be >= 1");
+        if (c[i].nz != c[0].nz) return fail(OPO_EINVAL, at + "all instances must share nz");
+        if (!std::isfinite(c[i].deff_pm_per_v) || !std::isfinite(c[i].dk_per_mm) ||
+            !finite3(c[i].alpha_per_mm) || !finite3(c[i].db1_ps_per_mm) ||
+            !finite3(c[i].b2_fs2_per_mm) || !finite3(c[i].b3_fs3_per_mm))
+            return fail(OPO_EINVAL, at + "crystal coefficients must be finite");
+        for (int x = 0; x < 3; ++x) {
+            if (!(k[i].refl[x] >= 0.0 && k[i].refl[x] <= 1.0))
+                return fail(OPO_EINVAL, at + "reflectivities must lie in [0, 1]");
+        }
+        if (!finite3(k[i].delta_rad) || !std::isfinite(k[i].gdd_fs2) ||
+            !std::isfinite(k[i].eom_beta) || !std::isfinite(k[i].eom_fpm_thz))
+            return fail(OPO_EINVAL, at + "cavity parameters must be finite");
+
+        // step criterion of Sec. 2.4: the nonlinear change per step,
+        // kappa |A| dz, must stay well below one
+        double amax = std::hypot(f[i].pump_cw[0], f[i].pump_cw[1]);
+        if (f[i].init)
+            for (long long q = 0; q < 3LL * nt; ++q)
+                amax = std::max(amax, std::hypot(f[i].init[2 * q], f[i].init[2 * q + 1]));
+        if (f[i].pump_in)
+            for (long long q = 0; q < nt; ++q)
+                amax = std::max(amax, std::hypot(f[i].pump_in[2 * q], f[i].pump_in[2 * q + 1]));
+        if (!std::isfinite(amax)) return fail(OPO_EINVAL, at + "initial fields must be finite");
+        double kmax = 0.0;
+        for (int x = 0; x < 3; ++x)
+            kmax = std::max(kmax, std::fabs(kTwoPi * c[i].deff_pm_per_v / (f[i].n[x] * f[i].lambda_um[x]) * 1e-9));
+        const double step = kmax * amax * c[i].length_mm / c[i].nz;
+        if (!(step < 0.5))
+            return fail(OPO_EINVAL, at + "step too large for the field amplitudes (kappa |A| dz = " +
+                                        std::to_string(step) + ", needs < 0.5)");
+    }
+    return OPO_OK;
+}
+
+static void build_twiddles_rows(std::vector<double> &re, std::vector<double> &im, long long n,
+                                long long count, double scale)
+{
+    // e^{-2 pi i q scale / n}, q < count, in FP64
+    for (long long q = 0; q < count; ++q) {
+        const double a = kTwoPi * static_cast<double>(q) * scale / static_cast<double>(n);
+        re.push_back(std::cos(a));
+        im.push_back(-std::sin(a));
+    }
+}
+
+template <typename R> static void upload_cplx(void *dst, const std::vector<double> &re,
+                                              const std::vector<double> &im, hipStream_t st)
+{
+    std::vector<R> buf(2 * re.size());
+    for (size_t i = 0; i < re.size(); ++i) {
+        buf[2 * i] = static_cast<R>(re[i]);
+        buf[2 * i + 1] = static_cast<R>(im[i]);
+    }
+    (void)hipMemcpyAsync(dst, buf.data(), buf.size() * sizeof(R), hipMemcpyHostToDevice, st);
+    (void)hipStreamSynchronize(st);
+}
+
+template <typename R> static void host_to_state(void *dst, const double *src, long long count,
+                                                hipStream_t st)
+{
+    std::vector<R> buf(2 * count);
+    for (long long i = 0; i < 2 * count; ++i)
+        buf[i] = static_cast<R>(src[i]);
+    (void)hipMemcpyAsync(dst, buf.data(), buf.size() * sizeof(R), hipMemcpyHostToDevice, st);
+    (void)hipStreamSynchronize(st);
+}
+
+template <typename R> static hipError_t state_to_host(double *dst, const void *src, long long count,
+                                                      hipStream_t st)
+{
+    std::vector<R> buf(2 * count);
+    hipError_t e = hipMemcpyAsync(buf.data(), src, buf.size() * sizeof(R), hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    for (long long i = 0; i < 2 * count; ++i)
+        dst[i] = static_cast<double>(buf[i]);
+    return hipSuccess;
+}
+
+static void release(opo_t *h)
+{
+    if (!h) return;
+    (void)hipSetDevice(h->device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    if (h->own_state && h->state) (void)hipFree(h->state);
+    void *bufs[] = {h->pump, h->d_inst, h->d_tile_a, h->d_tile_b, h->d_tw, h->d_tw4,
+                    h->d_partial, h->d_hist, h->d_counter, h->scratch};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        g_live.erase(h);
+    }
+    delete h;
+}
+
+template <typename R> static StepArgs<R> base_args(opo_t *h, void *state)
+{
+    StepArgs<R> a{};
+    a.inst = h->d_inst;
+    a.state = static_cast<cplx<R> *>(state);
+    a.pump = static_cast<const cplx<R> *>(h->pump);
+    a.tw = static_cast<const cplx<R> *>(h->d_tw);
+    a.tw4 = static_cast<const cplx<R> *>(h->d_tw4);
+    a.partial = h->d_partial;
+    a.nz = h->nz;
+    return a;
+}
+
+template <typename R> static void launch_a(opo_t *h, StepArgs<R> a, int flags, int step)
+{
+    a.tile_inst = h->d_tile_a;
+    a.flags = flags;
+    a.step = step;
+    column_pass<R><<<h->tiles_a, kThreads, h->lds_a, h->stream>>>(a);
+}
+
+template <typename R> static void launch_b(opo_t *h, StepArgs<R> a, int flags)
+{
+    a.tile_inst = h->d_tile_b;
+    a.flags = flags;
+    row_pass<R><<<h->tiles_b, kThreads, h->lds_b, h->stream>>>(a);
+}
+
+// One crystal pass of nz steps. `first` flags are OR-ed into the opening
+// column pass (refresh), `last` into the closing one (energy, mirror, EOM).
+template <typename R>
+static void enqueue_pass(opo_t *h, StepArgs<R> a, int nz, int first, int last)
+{
+    launch_a<R>(h, a, first | A_RK_THIS | A_FWD, 0);
+    for (int j = 0; j < nz; ++j) {
+        launch_b<R>(h, a, B_DISP);
+        if (j + 1 < nz) launch_a<R>(h, a, A_INV | A_RK_PREV | A_RK_THIS | A_FWD, j + 1);
+        else launch_a<R>(h, a, A_INV | A_RK_PREV | last, nz);
+    }
+}
+
+// One cavity round trip (loop order of Sec. 4.1).
+template <typename R> static void enqueue_roundtrip(opo_t *h)
+{
+    StepArgs<R> a = base_args<R>(h, h->state);
+    a.dz_arg = 0.0;
+    a.zbase = 0.0;
+    const int eom = h->any_eom ? A_EOM : 0;
+    if (h->any_gdd) {
+        enqueue_pass<R>(h, a, h->nz, A_REFRESH, A_ENERGY | A_FWD);
+        launch_b<R>(h, a, B_GDD);
+        launch_a<R>(h, a, A_INV | A_MIRROR | eom, 0);
+    } else {
+        enqueue_pass<R>(h, a, h->nz, A_REFRESH, A_ENERGY | A_MIRROR | eom);
+    }
+    energy_reduce<<<1, kThreads, 0, h->stream>>>(h->d_inst, h->n_inst, h->d_partial, h->d_hist,
+                                                 h->d_counter, kHistChunk);
+}
+
+template <typename R> static int setup_kernels(opo_t *h)
+{
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&column_pass<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(h->lds_a)));
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&row_pass<R>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(h->lds_b)));
+    return OPO_OK;
+}
+
+static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crystal_t *c,
+                     const opo_cavity_t *k, const opo_options_t *opt_in)
+{
+    opo_options_t opt{};
+    if (opt_in) opt = *opt_in;
+    if (opt.precision != OPO_F32 && opt.precision != OPO_F64)
+        return fail(OPO_EINVAL, "precision must be OPO_F32 or OPO_F64");
+    int rc = validate(n, f, c, k, opt.precision);
+    if (rc) return rc;
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= opt.device || opt.device < 0)
+        return fail(OPO_EDEVICE, "no HIP device with ordinal " + std::to_string(opt.device));
+    HIP_TRY(hipSetDevice(opt.device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, opt.device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(OPO_EDEVICE, std::string("device is ") + prop.gcnArchName + ", library built for gfx950");
+
+    opo_t *h = new (std::nothrow) opo_s();
+    if (!h) return fail(OPO_ENOMEM, "handle allocation failed");
+    h->precision = opt.precision;
+    h->device = opt.device;
+    h->n_inst = n;
+    h->nz = c[0].nz;
+    h->elem = opt.precision == OPO_F64 ? 16 : 8;
+    h->use_graph = opt.use_graph >= 0 ? 1 : 0;
+    const int tile_a = opt.tile_a > 0 ? opt.tile_a : default_tile_a(opt.precision);
+    const int tile_b = opt.tile_b > 0 ? opt.tile_b : default_tile_b(opt.precision);
+
+    auto bail = [&](int code) {
+        release(h);
+        return code;
+    };
+
+    if (opt.stream) {
+        h->stream = static_cast<hipStream_t>(opt.stream);
+    } else {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(OPO_EDEVICE, "hipStreamCreate failed"));
+        h->own_stream = true;
+    }
+
+    // ---- plan and per-instance descriptors
+    const uint64_t need = opo_state_bytes(n, f, opt.precision);
+    long long off = 0, pump_elems = 0;
+    std::vector<double> t4re, t4im;
+    std::vector<int> tile_a_inst, tile_b_inst;
+    size_t max_a = 0, max_b = 0;
+    h->inst.resize(n);
+    for (int i = 0; i < n; ++i) {
+        InstDesc &d = h->inst[i];
+        std::memset(&d, 0, sizeof(d));
+        const Plan p = make_plan(f[i].nt, opt.precision, tile_a, tile_b);
+        d.nt = f[i].nt;
+        d.log2nt = ilog2(d.nt);
+        d.n1 = 1 << p.log2n1;
+        d.log2n1 = p.log2n1;
+        d.n2 = 1 << p.log2n2;
+        d.log2n2 = p.log2n2;
+        d.log2cols = p.log2cols;
+        d.log2rows = p.log2rows;
+        d.off = off;
+        off += 3LL * d.nt;
+        d.pump_off = -1;
+        if (f[i].pump_in) {
+            d.pump_off = pump_elems;
+            pump_elems += d.nt;
+        }
+        d.tile_a0 = h->tiles_a;
+        d.tiles_a = d.n1 >> p.log2cols;
+        h->tiles_a += d.tiles_a;
+        for (int t = 0; t < d.tiles_a; ++t) tile_a_inst.push_back(i);
+        d.tile_b0 = h->tiles_b;
+        d.tiles_b = 3 * (d.n2 >> p.log2rows);
+        h->tiles_b += d.tiles_b;
+        for (int t = 0; t < d.tiles_b; ++t) tile_b_inst.push_back(i);
+        max_a = std::max(max_a, static_cast<size_t>(3) << (p.log2n2 + p.log2cols));
+        max_b = std::max(max_b, static_cast<size_t>(1) << (p.log2n1 + p.log2rows));
+        // shapes the kernels rely on: a tile fits the per-thread register
+        // budget of an FFT stage, and the butterfly twiddle table covers the
+        // transform lengths
+        const long long maxpts = static_cast<long long>(kThreads) *
+                                 (opt.precision == OPO_F64 ? max_pts<double>() : max_pts<float>());
+        if ((3LL << (p.log2n2 + p.log2cols)) > maxpts || (1LL << (p.log2n1 + p.log2rows)) > maxpts ||
+            d.n1 > kTwL || d.n2 > kTwL || p.log2cols > p.log2n1 || p.log2rows > p.log2n2 ||
+            static_cast<long long>(d.n1) * d.n2 != d.nt)
+            return bail(fail(OPO_EINVAL, "internal: tile plan out of bounds for nt " + std::to_string(d.nt)));
+
+        // four-step twiddles e^{-2 pi i m/nt}: low table m < 2^b, high table (m >> b) << b
+        const int bits = (d.log2nt + 1) / 2;
+        d.tw4_off = static_cast<int>(t4re.size());
+        d.tw4_bits = bits;
+        build_twiddles_rows(t4re, t4im, d.nt, 1LL << bits, 1.0);
+        build_twiddles_rows(t4re, t4im, d.nt, d.nt >> bits, static_cast<double>(1LL << bits));
+
+        int res = 0, gdd = 0, eom = 0;
+        for (int x = 0; x < 3; ++x) {
+            if (k[i].resonant[x]) res |= 1 << x;
+            if (k[i].gdd_on[x] && k[i].gdd_fs2 != 0.0) gdd |= 1 << x;
+            if (k[i].eom_on[x] && k[i].eom_beta != 0.0) eom |= 1 << x;
+        }
+        d.res_mask = res;
+        d.gdd_mask = gdd;
+        d.eom_mask = eom;
+        h->any_gdd |= gdd != 0;
+        h->any_eom |= eom != 0;
+
+        const double T = f[i].t_window_ps;
+        d.length_mm = c[i].length_mm;
+        for (int x = 0; x < 3; ++x) {
+            // Sec. 2.1: kappa = 2 pi d_eff/(n lambda); pm/V over um, then per mm
+            d.kappa[x] = kTwoPi * c[i].deff_pm_per_v / (f[i].n[x] * f[i].lambda_um[x]) * 1e-9;
+            // Eq. 5 phase per mm in revolutions for bin ks (w = 2 pi ks/T):
+            // (-db1 w + b2 w^2/2 - b3 w^3/6)/(2 pi)
+            const double b2 = c[i].b2_fs2_per_mm[x] * 1e-6, b3 = c[i].b3_fs3_per_mm[x] * 1e-9;
+            d.disp[x][0] = -c[i].db1_ps_per_mm[x] / T;
+            d.disp[x][1] = kPi * b2 / (T * T);
+            d.disp[x][2] = -kTwoPi * kTwoPi * b3 / (6.0 * T * T * T);
+            d.alpha_half[x] = 0.5 * c[i].alpha_per_mm[x];
+            const double sr = std::sqrt(k[i].refl[x]);
+            d.mirror[x][0] = sr * std::cos(k[i].delta_rad[x]);
+            d.mirror[x][1] = sr * std::sin(k[i].delta_rad[x]);
+        }
+        d.dk_rev = c[i].dk_per_mm / kTwoPi;
+        d.gdd_rev = kPi * k[i].gdd_fs2 * 1e-6 / (T * T);   // gamma w^2/2 / (2 pi)
+        d.eom_beta = k[i].eom_beta;
+        d.eom_rev0 = -0.5 * T * k[i].eom_fpm_thz;             // f t_0
+        d.eom_rev_step = k[i].eom_fpm_thz * T / d.nt;          // f dt
+        d.pump_cw[0] = f[i].pump_cw[0];
+        d.pump_cw[1] = f[i].pump_cw[1];
+
+    }
+
+    // ---- device memory
+    if (opt.state) {
+        if (opt.state_bytes < need)
+            return bail(fail(OPO_EINVAL, "caller state buffer is smaller than opo_state_bytes()"));
+        h->state = opt.state;
+    } else {
+        if (hipMalloc(&h->state, need) != hipSuccess)
+            return bail(fail(OPO_ENOMEM, "hipMalloc of the field state failed"));
+        h->own_state = true;
+    }
+    h->state_bytes = need;
+    const size_t es = h->elem;
+    if (pump_elems && hipMalloc(&h->pump, pump_elems * es) != hipSuccess)
+        return bail(fail(OPO_ENOMEM, "hipMalloc of the input pump failed"));
+    if (hipMalloc(reinterpret_cast<void **>(&h->d_inst), n * sizeof(InstDesc)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&h->d_tile_a), h->tiles_a * sizeof(int)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&h->d_tile_b), h->tiles_b * sizeof(int)) != hipSuccess ||
+        hipMalloc(&h->d_tw, static_cast<size_t>(kTwL) * es) != hipSuccess ||
+        hipMalloc(&h->d_tw4, t4re.size() * es) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&h->d_partial), h->tiles_a * 3 * sizeof(double)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&h->d_hist),
+                  static_cast<size_t>(kHistChunk) * n * 3 * sizeof(double)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&h->d_counter), sizeof(int)) != hipSuccess)
+        return bail(fail(OPO_ENOMEM, "hipMalloc of the tables failed"));
+
+    h->lds_a = (opt.precision == OPO_F64 ? lds_elems<double>(static_cast<int>(max_a))
+                                         : lds_elems<float>(static_cast<int>(max_a))) * es;
+    h->lds_b = (opt.precision == OPO_F64 ? lds_elems<double>(static_cast<int>(max_b))
+                                         : lds_elems<float>(static_cast<int>(max_b))) * es;
+    if (h->lds_a > 160 * 1024 || h->lds_b > 160 * 1024)
+        return bail(fail(OPO_EINVAL, "internal: tile needs more LDS than a workgroup has"));
+
+    std::vector<double> twre, twim;
+    build_twiddles_rows(twre, twim, kTwL, kTwL, 1.0);
+    hipStream_t st = h->stream;
+    if (hipMemcpyAsync(h->d_inst, h->inst.data(), n * sizeof(InstDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(h->d_tile_a, tile_a_inst.data(), tile_a_inst.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(h->d_tile_b, tile_b_inst.data(), tile_b_inst.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+        return bail(fail(OPO_EDEVICE, "upload of the instance tables failed"));
+    if (opt.precision == OPO_F64) {
+        upload_cplx<double>(h->d_tw, twre, twim, st);
+        upload_cplx<double>(h->d_tw4, t4re, t4im, st);
+    } else {
+        upload_cplx<float>(h->d_tw, twre, twim, st);
+        upload_cplx<float>(h->d_tw4, t4re, t4im, st);
+    }
+    std::vector<double> zeros;
+    for (int i = 0; i < n; ++i) {
+        const InstDesc &d = h->inst[i];
+        const double *src = f[i].init;
+        if (!src) {
+            zeros.assign(6 * static_cast<size_t>(d.nt), 0.0);
+            src = zeros.data();
+        }
+        char *dst = static_cast<char *>(h->state) + d.off * es;
+        if (opt.precision == OPO_F64) host_to_state<double>(dst, src, 3LL * d.nt, st);
+        else host_to_state<float>(dst, src, 3LL * d.nt, st);
+        if (f[i].pump_in) {
+            char *pd = static_cast<char *>(h->pump) + d.pump_off * es;
+            if (opt.precision == OPO_F64) host_to_state<double>(pd, f[i].pump_in, d.nt, st);
+            else host_to_state<float>(pd, f[i].pump_in, d.nt, st);
+        }
+    }
+    int krc = opt.precision == OPO_F64 ? setup_kernels<double>(h) : setup_kernels<float>(h);
+    if (krc) return bail(krc);
+    hipError_t le = hipGetLastError();
+    if (le != hipSuccess) return bail(fail(OPO_EDEVICE, std::string("init: ") + hipGetErrorString(le)));
+    for (int i = 0; i < n; ++i) h->t_window.push_back(f[i].t_window_ps);
+    {
+        std::lock_guard<std::mutex> lk(g_live_mu);
+        g_live.insert(h);
+    }
+    *out = h;
+    return OPO_OK;
+}
+
+static int check(opo_t *h)
+{
+    if (!is_live(h)) return fail(OPO_ESTATE, "invalid or destroyed handle");
+    if (hipSetDevice(h->device) != hipSuccess) return fail(OPO_EDEVICE, "hipSetDevice failed");
+    return OPO_OK;
+}
+
+template <typename R> static int propagate_impl(opo_t *h, int nz, double dz)
+{
+    StepArgs<R> a = base_args<R>(h, h->state);
+    a.dz_arg = dz;
+    a.zbase = h->z;
+    enqueue_pass<R>(h, a, nz, 0, 0);
+    HIP_TRY(hipGetLastError());
+    h->z += nz * dz;
+    return OPO_OK;
+}
+
+template <typename R> static int roundtrip_impl(opo_t *h, int n_rt)
+{
+    if (h->use_graph && !h->graph) {
+        hipGraph_t g;
+        HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        enqueue_roundtrip<R>(h);
+        hipError_t ce = hipStreamEndCapture(h->stream, &g);
+        if (ce != hipSuccess) return fail(OPO_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+        ce = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ce != hipSuccess) {
+            h->graph = nullptr;
+            return fail(OPO_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ce));
+        }
+    }
+    int bad = -1;
+    int done = 0;
+    std::vector<double> chunk;
+    while (done < n_rt) {
+        const int m = std::min(kHistChunk, n_rt - done);
+        set_counter<<<1, 1, 0, h->stream>>>(h->d_counter, 0);
+        for (int r = 0; r < m; ++r) {
+            if (h->graph) {
+                HIP_TRY(hipGraphLaunch(h->graph, h->stream));
+            } else {
+                enqueue_roundtrip<R>(h);
+            }
+        }
+        HIP_TRY(hipGetLastError());
+        chunk.resize(static_cast<size_t>(m) * h->n_inst * 3);
+        HIP_TRY(hipMemcpyAsync(chunk.data(), h->d_hist, chunk.size() * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        for (size_t q = 0; q < chunk.size(); ++q)
+            if (bad < 0 && !std::isfinite(chunk[q]))
+                bad = h->hist_rows + static_cast<int>(q / (3 * h->n_inst));
+        h->hist.insert(h->hist.end(), chunk.begin(), chunk.end());
+        h->hist_rows += m;
+        done += m;
+    }
+    h->z = 0.0;
+    if (bad >= 0)
+        return fail(OPO_ENONFINITE, "non-finite energy at round trip " + std::to_string(bad));
+    return OPO_OK;
+}
+
+template <typename R> static int spectrum_impl(opo_t *h, int inst, int field, double *out)
+{
+    const InstDesc &d = h->inst[inst];
+    if (!h->scratch) {
+        if (hipMalloc(&h->scratch, h->state_bytes) != hipSuccess)
+            return fail(OPO_ENOMEM, "hipMalloc of the spectrum scratch failed");
+    }
+    HIP_TRY(hipMemcpyAsync(h->scratch, h->state, h->state_bytes, hipMemcpyDeviceToDevice, h->stream));
+    StepArgs<R> a = base_args<R>(h, h->scratch);
+    launch_a<R>(h, a, A_FWD, 0);
+    launch_b<R>(h, a, B_FWD_ONLY);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> tmp(2 * static_cast<size_t>(d.nt));
+    const char *src = static_cast<const char *>(h->scratch) + (d.off + static_cast<long long>(field) * d.nt) * h->elem;
+    HIP_TRY(state_to_host<R>(tmp.data(), src, d.nt, h->stream));
+    // position k2*n1 + k1 holds bin k2 + n2*k1
+    for (int k2 = 0; k2 < d.n2; ++k2)
+        for (int k1 = 0; k1 < d.n1; ++k1) {
+            const long long pos = static_cast<long long>(k2) * d.n1 + k1;
+            const long long bin = k2 + static_cast<long long>(d.n2) * k1;
+            out[2 * bin] = tmp[2 * pos];
+            out[2 * bin + 1] = tmp[2 * pos + 1];
+        }
+    return OPO_OK;
+}
+
+} // namespace opo
+
+extern "C" {
+
+uint64_t opo_state_bytes(int32_t n, const opo_fields_t *fields, int32_t precision)
+{
+    if (n <= 0 || !fields) return 0;
+    uint64_t s = 0;
+    for (int i = 0; i < n; ++i)
+        s += 3ULL * static_cast<uint64_t>(fields[i].nt > 0 ? fields[i].nt : 0);
+    return s * (precision == OPO_F64 ? 16 : 8);
+}
+
+int opo_init(opo_t **h, const opo_fields_t *fields, const opo_crystal_t *crystal,
+             const opo_cavity_t *cavity, const opo_options_t *options)
+{
+    return opo_init_batch(h, 1, fields, crystal, cavity, options);
+}
+
+int opo_init_batch(opo_t **h, int32_t n, const opo_fields_t *fields, const opo_crystal_t *crystals,
+                   const opo_cavity_t *cavities, const opo_options_t *options)
+{
+    if (!h) return fail(OPO_EINVAL, "handle pointer is NULL");
+    *h = nullptr;
+    if (n < 1 || !fields || !crystals || !cavities)
+        return fail(OPO_EINVAL, "need n >= 1 and non-NULL fields, crystals and cavities");
+    try {
+        g_err.clear();
+        return init_impl(h, n, fields, crystals, cavities, options);
+    } catch (const std::bad_alloc &) {
+        return fail(OPO_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(OPO_EDEVICE, "unexpected exception in opo_init");
+    }
+}
+
+int ssfm_propagate(opo_t *h, int32_t nz, double dz)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    if (nz < 1 || !(dz > 0.0) || !std::isfinite(dz)) return fail(OPO_EINVAL, "need nz >= 1 and finite dz > 0");
+    try {
+        return h->precision == OPO_F64 ? propagate_impl<double>(h, nz, dz) : propagate_impl<float>(h, nz, dz);
+    } catch (...) {
+        return fail(OPO_EDEVICE, "unexpected exception in ssfm_propagate");
+    }
+}
+
+int cavity_roundtrip(opo_t *h, int32_t n_rt)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    if (n_rt < 0) return fail(OPO_EINVAL, "n_rt must be >= 0");
+    try {
+        return h->precision == OPO_F64 ? roundtrip_impl<double>(h, n_rt) : roundtrip_impl<float>(h, n_rt);
+    } catch (const std::bad_alloc &) {
+        return fail(OPO_ENOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(OPO_EDEVICE, "unexpected exception in cavity_roundtrip");
+    }
+}
+
+int opo_sync(opo_t *h)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return OPO_OK;
+}
+
+int opo_get_fields(opo_t *h, int32_t inst, int32_t field, int32_t domain, double *out)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    if (inst < 0 || inst >= h->n_inst || field < 0 || field > 2 || !out || domain < 0 || domain > 1)
+        return fail(OPO_EINVAL, "bad instance, field, domain or output pointer");
+    try {
+        if (domain == 1)
+            return h->precision == OPO_F64 ? spectrum_impl<double>(h, inst, field, out)
+                                           : spectrum_impl<float>(h, inst, field, out);
+        const InstDesc &d = h->inst[inst];
+        const char *src = static_cast<const char *>(h->state) + (d.off + static_cast<long long>(field) * d.nt) * h->elem;
+        HIP_TRY(h->precision == OPO_F64 ? state_to_host<double>(out, src, d.nt, h->stream)
+                                        : state_to_host<float>(out, src, d.nt, h->stream));
+        return OPO_OK;
+    } catch (...) {
+        return fail(OPO_ENOMEM, "host allocation failed");
+    }
+}
+
+int opo_set_fields(opo_t *h, int32_t inst, int32_t field, const double *in)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    if (inst < 0 || inst >= h->n_inst || field < 0 || field > 2 || !in)
+        return fail(OPO_EINVAL, "bad instance, field or input pointer");
+    try {
+        const InstDesc &d = h->inst[inst];
+        char *dst = static_cast<char *>(h->state) + (d.off + static_cast<long long>(field) * d.nt) * h->elem;
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        if (h->precision == OPO_F64) host_to_state<double>(dst, in, d.nt, h->stream);
+        else host_to_state<float>(dst, in, d.nt, h->stream);
+        HIP_TRY(hipGetLastError());
+        h->z = 0.0;
+        return OPO_OK;
+    } catch (...) {
+        return fail(OPO_ENOMEM, "host allocation failed");
+    }
+}
+
+int opo_get_energy_history(opo_t *h, int32_t inst, double *out, int32_t capacity, int32_t *rows)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    if (inst < 0 || inst >= h->n_inst || capacity < 0 || (capacity > 0 && !out))
+        return fail(OPO_EINVAL, "bad instance, capacity or output pointer");
+    const int m = std::min(capacity, h->hist_rows);
+    for (int r = 0; r < m; ++r)
+        for (int x = 0; x < 3; ++x)
+            out[3 * r + x] = h->hist[(static_cast<size_t>(r) * h->n_inst + inst) * 3 + x];
+    if (rows) *rows = h->hist_rows;
+    return OPO_OK;
+}
+
+int opo_get_grid(opo_t *h, int32_t inst, double *t, double *omega)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    if (inst < 0 || inst >= h->n_inst) return fail(OPO_EINVAL, "bad instance");
+    const int nt = h->inst[inst].nt;
+    const double T = h->t_window[inst];
+    for (int j = 0; j < nt; ++j) {
+        if (t) t[j] = -0.5 * T + j * (T / nt);
+        if (omega) omega[j] = kTwoPi * (j < nt / 2 ? j : j - nt) / T;
+    }
+    return OPO_OK;
+}
+
+int opo_info(opo_t *h, int32_t *n_instances, double *z_mm)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    if (n_instances) *n_instances = h->n_inst;
+    if (z_mm) *z_mm = h->z;
+    return OPO_OK;
+}
+
+int opo_destroy(opo_t *h)
+{
+    if (!is_live(h)) return fail(OPO_ESTATE, "invalid or destroyed handle");
+    release(h);
+    return OPO_OK;
+}
+
+const char *opo_last_error(void) { return g_err.c_str(); }
+
+} // extern "C"

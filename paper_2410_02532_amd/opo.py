@@ -1,0 +1,255 @@
+"""Python binding of the gfx950 C-ABI library ``libopo.so`` (include/opo.h).
+
+Argument marshalling only: every step of the propagation runs in the HIP
+kernels behind the C ABI. PyTorch supplies the device memory that holds the
+fields and the stream the library runs on. The library must be built
+(``python -m paper_2410_02532_amd.build``); there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libopo.so")
+
+OPO_OK, OPO_EINVAL, OPO_ENOMEM, OPO_EDEVICE, OPO_ENONFINITE, OPO_ESTATE = 0, -1, -2, -3, -4, -5
+OPO_F32, OPO_F64 = 0, 1
+STATUS = {0: "OPO_OK", -1: "OPO_EINVAL", -2: "OPO_ENOMEM", -3: "OPO_EDEVICE",
+          -4: "OPO_ENONFINITE", -5: "OPO_ESTATE"}
+
+EXPORTS = ("opo_state_bytes", "opo_init", "opo_init_batch", "ssfm_propagate", "cavity_roundtrip",
+           "opo_sync", "opo_get_fields", "opo_set_fields", "opo_get_energy_history",
+           "opo_get_grid", "opo_info", "opo_destroy", "opo_last_error")
+
+_d3 = ctypes.c_double * 3
+_i3 = ctypes.c_int32 * 3
+_d2 = ctypes.c_double * 2
+
+
+class FieldsT(ctypes.Structure):
+    _fields_ = [("nt", ctypes.c_int32), ("t_window_ps", ctypes.c_double), ("lambda_um", _d3),
+                ("n", _d3), ("init", ctypes.POINTER(ctypes.c_double)),
+                ("pump_in", ctypes.POINTER(ctypes.c_double)), ("pump_cw", _d2)]
+
+
+class CrystalT(ctypes.Structure):
+    _fields_ = [("length_mm", ctypes.c_double), ("nz", ctypes.c_int32),
+                ("deff_pm_per_v", ctypes.c_double), ("dk_per_mm", ctypes.c_double),
+                ("alpha_per_mm", _d3), ("db1_ps_per_mm", _d3), ("b2_fs2_per_mm", _d3),
+                ("b3_fs3_per_mm", _d3)]
+
+
+class CavityT(ctypes.Structure):
+    _fields_ = [("resonant", _i3), ("refl", _d3), ("delta_rad", _d3), ("gdd_fs2", ctypes.c_double),
+                ("gdd_on", _i3), ("eom_beta", ctypes.c_double), ("eom_fpm_thz", ctypes.c_double),
+                ("eom_on", _i3)]
+
+
+class OptionsT(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("stream", ctypes.c_void_p), ("state", ctypes.c_void_p),
+                ("state_bytes", ctypes.c_uint64), ("tile_a", ctypes.c_int32),
+                ("tile_b", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class OpoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS.get(code, code), msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libopo.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libopo.so is not built; run `python -m paper_2410_02532_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    lib.opo_state_bytes.argtypes = [I, ctypes.POINTER(FieldsT), I]
+    lib.opo_state_bytes.restype = ctypes.c_uint64
+    lib.opo_init.argtypes = [ctypes.POINTER(P), ctypes.POINTER(FieldsT), ctypes.POINTER(CrystalT),
+                             ctypes.POINTER(CavityT), ctypes.POINTER(OptionsT)]
+    lib.opo_init_batch.argtypes = [ctypes.POINTER(P), I, ctypes.POINTER(FieldsT),
+                                   ctypes.POINTER(CrystalT), ctypes.POINTER(CavityT),
+                                   ctypes.POINTER(OptionsT)]
+    lib.ssfm_propagate.argtypes = [P, I, D]
+    lib.cavity_roundtrip.argtypes = [P, I]
+    lib.opo_sync.argtypes = [P]
+    lib.opo_get_fields.argtypes = [P, I, I, I, P]
+    lib.opo_set_fields.argtypes = [P, I, I, P]
+    lib.opo_get_energy_history.argtypes = [P, I, P, I, ctypes.POINTER(I)]
+    lib.opo_get_grid.argtypes = [P, I, P, P]
+    lib.opo_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(D)]
+    lib.opo_destroy.argtypes = [P]
+    lib.opo_last_error.argtypes = []
+    lib.opo_last_error.restype = ctypes.c_char_p
+    for name in ("opo_init", "opo_init_batch", "ssfm_propagate", "cavity_roundtrip", "opo_sync",
+                 "opo_get_fields", "opo_set_fields", "opo_get_energy_history", "opo_get_grid",
+                 "opo_info", "opo_destroy"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def last_error():
+    return load().opo_last_error().decode()
+
+
+def _check(code):
+    if code != OPO_OK:
+        raise OpoError(code, last_error())
+    return code
+
+
+def _structs(instances, nz):
+    """ctypes arrays for a list of instance dicts (crystal, cavity, fields, pump_in)."""
+    n = len(instances)
+    fields, crystals, cavities = (FieldsT * n)(), (CrystalT * n)(), (CavityT * n)()
+    keep = []
+    for i, ins in enumerate(instances):
+        cr, cav = ins["crystal"], ins["cavity"]
+        f = fields[i]
+        f.nt = int(cr["nt"])
+        f.t_window_ps = cr["t_window_ps"]
+        f.lambda_um = _d3(*cr["lambda_um"])
+        f.n = _d3(*cr["n"])
+        init = np.ascontiguousarray(np.asarray(ins["fields"], dtype=np.complex128).reshape(3, f.nt))
+        keep.append(init)
+        f.init = init.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        pump = np.asarray(ins.get("pump_in", 0.0), dtype=np.complex128)
+        if pump.ndim == 0 or np.all(pump == pump.flat[0]):
+            v = complex(pump.flat[0]) if pump.size else 0j
+            f.pump_in = ctypes.POINTER(ctypes.c_double)()
+            f.pump_cw = _d2(v.real, v.imag)
+        else:
+            pump = np.ascontiguousarray(pump.reshape(f.nt))
+            keep.append(pump)
+            f.pump_in = pump.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            f.pump_cw = _d2(0.0, 0.0)
+        c = crystals[i]
+        c.length_mm = cr["length_mm"]
+        c.nz = int(nz)
+        c.deff_pm_per_v = cr["deff_pm_per_v"]
+        c.dk_per_mm = cr["dk_per_mm"]
+        c.alpha_per_mm = _d3(*cr["alpha_per_mm"])
+        c.db1_ps_per_mm = _d3(*cr["db1_ps_per_mm"])
+        c.b2_fs2_per_mm = _d3(*cr["b2_fs2_per_mm"])
+        c.b3_fs3_per_mm = _d3(*cr["b3_fs3_per_mm"])
+        k = cavities[i]
+        k.resonant = _i3(*[int(v) for v in cav["resonant"]])
+        k.refl = _d3(*cav["refl"])
+        k.delta_rad = _d3(*cav["delta_rad"])
+        k.gdd_fs2 = cav["gdd_fs2"]
+        k.gdd_on = _i3(*[int(v) for v in cav["gdd_on"]])
+        k.eom_beta = cav["eom_beta"]
+        k.eom_fpm_thz = cav["eom_fpm_thz"]
+        k.eom_on = _i3(*[int(v) for v in cav["eom_on"]])
+    return n, fields, crystals, cavities, keep
+
+
+class Opo:
+    """A handle over one or several OPO instances on one GPU.
+
+    instances: list of dicts with keys crystal, cavity, fields (3, nt), pump_in.
+    The field state lives in a torch uint8 tensor on ``device``; the library
+    runs on a torch stream (default priority) created for the handle.
+    """
+
+    def __init__(self, instances, nz, precision="f32", device=0, tile_a=0, tile_b=0,
+                 use_graph=True):
+        import torch
+        lib = load()
+        self._lib = lib
+        self.n, fields, crystals, cavities, keep = _structs(instances, nz)
+        self.nts = [int(ins["crystal"]["nt"]) for ins in instances]
+        self.precision = OPO_F64 if precision in ("f64", OPO_F64) else OPO_F32
+        nbytes = lib.opo_state_bytes(self.n, fields, self.precision)
+        self._dev = torch.device("cuda", device)
+        self._stream = torch.cuda.Stream(self._dev)   # default priority
+        self._state = torch.empty(int(nbytes), dtype=torch.uint8, device=self._dev)
+        self._state.record_stream(self._stream)
+        torch.cuda.current_stream(self._dev).synchronize()
+        opt = OptionsT(precision=self.precision, device=device,
+                       stream=ctypes.c_void_p(self._stream.cuda_stream),
+                       state=ctypes.c_void_p(self._state.data_ptr()), state_bytes=nbytes,
+                       tile_a=int(tile_a), tile_b=int(tile_b), use_graph=1 if use_graph else -1)
+        h = ctypes.c_void_p()
+        _check(lib.opo_init_batch(ctypes.byref(h), self.n, fields, crystals, cavities,
+                                  ctypes.byref(opt)))
+        del keep
+        self.h = h
+
+    # --- the three calls of the boundary
+    def ssfm_propagate(self, nz, dz):
+        _check(self._lib.ssfm_propagate(self.h, int(nz), float(dz)))
+
+    def cavity_roundtrip(self, n_rt):
+        return _check(self._lib.cavity_roundtrip(self.h, int(n_rt)))
+
+    def sync(self):
+        _check(self._lib.opo_sync(self.h))
+
+    def get_fields(self, inst=0, domain=0):
+        nt = self.nts[inst]
+        out = np.empty((3, nt), dtype=np.complex128)
+        for x in range(3):
+            buf = np.empty(nt, dtype=np.complex128)
+            _check(self._lib.opo_get_fields(self.h, inst, x, domain, buf.ctypes.data))
+            out[x] = buf
+        return out
+
+    def set_fields(self, a, inst=0):
+        nt = self.nts[inst]
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128).reshape(3, nt))
+        for x in range(3):
+            row = np.ascontiguousarray(a[x])
+            _check(self._lib.opo_set_fields(self.h, inst, x, row.ctypes.data))
+
+    def energy_history(self, inst=0):
+        rows = ctypes.c_int32()
+        _check(self._lib.opo_get_energy_history(self.h, inst, None, 0, ctypes.byref(rows)))
+        out = np.zeros((rows.value, 3))
+        if rows.value:
+            _check(self._lib.opo_get_energy_history(self.h, inst, out.ctypes.data, rows.value,
+                                                    ctypes.byref(rows)))
+        return out
+
+    def grid(self, inst=0):
+        nt = self.nts[inst]
+        t, w = np.empty(nt), np.empty(nt)
+        _check(self._lib.opo_get_grid(self.h, inst, t.ctypes.data, w.ctypes.data))
+        return t, w
+
+    def info(self):
+        n, z = ctypes.c_int32(), ctypes.c_double()
+        _check(self._lib.opo_info(self.h, ctypes.byref(n), ctypes.byref(z)))
+        return n.value, z.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            _check(self._lib.opo_destroy(self.h))
+            self.h = None
+            self._state = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def from_workload(w, precision=None, **kw):
+    """Handle for a workload dict of the workloads module (single or batched)."""
+    insts = w["instances"] if "instances" in w else [w]
+    return Opo(insts, w["nz"], precision=precision or w.get("precision", "f32"), **kw)

@@ -1,0 +1,112 @@
+"""The C-ABI library loads, exports every symbol include/opo.h declares, and
+rejects bad arguments on the host side (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2410_02532_amd import opo as B
+from paper_2410_02532_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "opo.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("opo_init", "ssfm_propagate", "cavity_roundtrip"):
+        assert must in names
+    assert sorted(B.EXPORTS) == names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+        assert isinstance(getattr(lib, name), ctypes._CFuncPtr)
+
+
+def _one(nt=64, nz=10, **cav):
+    cr = W.crystal(nt)
+    ins = dict(crystal=cr, cavity=W.cavity(**cav), fields=W.initial_fields(nt, 1e6, 1),
+               pump_in=np.full(nt, 1e6 + 0j))
+    return B._structs([ins], nz)
+
+
+def _init(fields, crystals, cavities, n=1, precision=0):
+    lib = B.load()
+    h = ctypes.c_void_p()
+    opt = B.OptionsT(precision=precision)
+    rc = lib.opo_init_batch(ctypes.byref(h), n, fields, crystals, cavities, ctypes.byref(opt))
+    return rc, h
+
+
+def test_state_bytes():
+    lib = B.load()
+    n, f, c, k, keep = _one(nt=256)
+    assert lib.opo_state_bytes(1, f, 0) == 3 * 256 * 8
+    assert lib.opo_state_bytes(1, f, 1) == 3 * 256 * 16
+    assert lib.opo_state_bytes(0, f, 0) == 0
+
+
+@pytest.mark.parametrize("mutate, what", [
+    (lambda f, c, k: setattr(f[0], "nt", 96), "power of two"),
+    (lambda f, c, k: setattr(f[0], "nt", 1), "power of two"),
+    (lambda f, c, k: setattr(f[0], "nt", 1 << 21), "power of two"),
+    (lambda f, c, k: setattr(f[0], "t_window_ps", -1.0), "t_window"),
+    (lambda f, c, k: setattr(c[0], "nz", 0), "nz"),
+    (lambda f, c, k: setattr(c[0], "length_mm", float("nan")), "length"),
+    (lambda f, c, k: k[0].refl.__setitem__(1, 1.5), "reflectivit"),
+    (lambda f, c, k: c[0].b2_fs2_per_mm.__setitem__(0, float("inf")), "finite"),
+    (lambda f, c, k: setattr(c[0], "deff_pm_per_v", 1e6), "step too large"),
+])
+def test_init_rejects_bad_arguments(mutate, what):
+    n, f, c, k, keep = _one()
+    mutate(f, c, k)
+    rc, h = _init(f, c, k)
+    assert rc == B.OPO_EINVAL
+    assert h.value is None
+    assert what in B.last_error()
+
+
+def test_batch_must_share_nz_and_bad_precision():
+    lib = B.load()
+    n, f, c, k, keep = _one()
+    f2, c2, k2 = (B.FieldsT * 2)(f[0], f[0]), (B.CrystalT * 2)(c[0], c[0]), (B.CavityT * 2)(k[0], k[0])
+    c2[1].nz = c2[0].nz + 1
+    rc, _ = _init(f2, c2, k2, n=2)
+    assert rc == B.OPO_EINVAL and "share nz" in B.last_error()
+    rc, _ = _init(f, c, k, precision=7)
+    assert rc == B.OPO_EINVAL
+    h = ctypes.c_void_p()
+    assert lib.opo_init_batch(ctypes.byref(h), 0, f, c, k, None) == B.OPO_EINVAL
+    assert lib.opo_init(None, f, c, k, None) == B.OPO_EINVAL
+
+
+def test_calls_on_invalid_handles():
+    lib = B.load()
+    bogus = ctypes.c_void_p(0x1234)
+    assert lib.ssfm_propagate(None, 10, 0.1) == B.OPO_ESTATE
+    assert lib.cavity_roundtrip(bogus, 1) == B.OPO_ESTATE
+    assert lib.opo_sync(None) == B.OPO_ESTATE
+    assert lib.opo_destroy(bogus) == B.OPO_ESTATE
+    out = np.zeros(8)
+    assert lib.opo_get_fields(None, 0, 0, 0, out.ctypes.data) == B.OPO_ESTATE
+    assert "handle" in B.last_error()
+
+
+def test_no_device_is_reported():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    n, f, c, k, keep = _one()
+    rc, h = _init(f, c, k)
+    assert rc == B.OPO_EDEVICE
+    assert h.value is None

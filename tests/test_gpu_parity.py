@@ -1,0 +1,217 @@
+"""Parity of the gfx950 HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Both sides receive the same seeded inputs from the workloads module. Bars:
+complex128 runs match the oracle to 1e-11 relative L2 per field and pass;
+complex64 runs (FP64 phase arguments and energies) to 1e-4 relative L2 per
+field and pass, and 1e-3 in round-trip energies, as the target of the method's
+FP32 path states. Bit-exact equalities hold where the same kernels run on
+the same data (batch vs single, graph vs plain launches, repeated runs, a pass
+split in two calls).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import torch  # noqa: F401  (imported at collection: the first import can take minutes)
+
+import oracle
+from paper_2410_02532_amd import opo as B
+from paper_2410_02532_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-11, "f32": 1e-4}
+TOL_E = {"f64": 1e-10, "f32": 1e-3}
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel_l2(got, ref):
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def rel_max(got, ref):
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+def _stress(nt, seed=0, t_window=40.0, deff=60.0, b3=300.0, dk=0.4, alpha=(0.02, 0.01, 0.03)):
+    """Pulsed pump, seeded signal and idler, every term of Eqs. 2-5 switched on."""
+    cr = W.crystal(nt, t_window_ps=t_window, deff=deff, b3=(b3, -0.5 * b3, 0.7 * b3), dk_per_mm=dk,
+                   alpha=alpha, db1=(0.25, 0.0, -0.15), b2=(250.0, 150.0, 100.0),
+                   n=(2.25, 2.2, 2.15))
+    t = W.time_grid(nt, t_window)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    pump = 2.0e6 * np.exp(-t * t / (2 * (0.2 * t_window) ** 2)) * np.exp(0.3j)
+    a = np.empty((3, nt), complex)
+    a[0] = pump
+    a[1] = 3.0e5 * np.exp(-(t - 1.0) ** 2 / (2 * (0.1 * t_window) ** 2)) + W.noise(nt, 1e3, seed + 1)
+    a[2] = W.noise(nt, 2e4, seed + 2) * rng.uniform(0.5, 1.5)
+    cav = W.cavity(resonant=(0, 1, 1), refl=(0.0, 0.9, 0.7), delta=(0.0, 0.2, -0.4))
+    return dict(crystal=cr, cavity=cav, fields=a, pump_in=pump)
+
+
+def _handle(inst, nz, precision, **kw):
+    return B.Opo([inst], nz, precision=precision, **kw)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+@pytest.mark.parametrize("nt", [2, 4, 8, 64, 512, 1 << 12, 1 << 14, 1 << 16])
+def test_pass_parity(nt, precision):
+    say("pass parity nt=%d %s" % (nt, precision))
+    ins = _stress(nt, seed=nt)
+    nz, dz = 20, 0.25
+    ref = oracle.ssfm_pass(ins["crystal"], ins["fields"], nz, dz)
+    with _handle(ins, nz, precision) as h:
+        h.ssfm_propagate(nz, dz)
+        got = h.get_fields()
+        assert h.info()[1] == pytest.approx(nz * dz)
+    for x in range(3):
+        assert rel_l2(got[x], ref[x]) <= TOL[precision], (x, rel_l2(got[x], ref[x]))
+        assert rel_max(got[x], ref[x]) <= 10 * TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_single_pass_workload(precision):
+    """The single-pass workload at its full size: Nt = 2^10, Nz = 100, CW pump, noise seeds."""
+    w = W.config("single_pass")
+    say("single pass workload", precision)
+    dz = w["crystal"]["length_mm"] / w["nz"]
+    ref = oracle.ssfm_pass(w["crystal"], w["fields"], w["nz"], dz)
+    with B.from_workload(w, precision=precision) as h:
+        h.ssfm_propagate(w["nz"], dz)
+        got = h.get_fields()
+    for x in range(3):
+        assert rel_l2(got[x], ref[x]) <= TOL[precision], (x, rel_l2(got[x], ref[x]))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_pass_split_in_two_calls_is_identical(precision):
+    ins = _stress(4096, seed=3)
+    with _handle(ins, 20, precision) as h1, _handle(ins, 20, precision) as h2:
+        h1.ssfm_propagate(20, 0.25)
+        h2.ssfm_propagate(10, 0.25)
+        h2.ssfm_propagate(10, 0.25)
+        assert np.array_equal(h1.get_fields(), h2.get_fields())
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_roundtrip_parity_sro(precision):
+    """CW singly resonant OPO above threshold, idler and pump non-resonant."""
+    say("round trips SRO", precision)
+    w = W.config("sro_cw", nt=1024, nz=25, level=4.0)
+    nrt = 40
+    ref, e_ref = oracle.roundtrips(w["crystal"], w["cavity"], w["fields"], w["pump_in"], w["nz"], nrt)
+    with B.from_workload(w, precision=precision) as h:
+        h.cavity_roundtrip(nrt)
+        e = h.energy_history()
+        got = h.get_fields()
+    assert e.shape == (nrt, 3)
+    for x in range(3):
+        assert np.max(np.abs(e[:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E[precision]
+        assert rel_l2(got[x], ref[x]) <= 10 * TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_roundtrip_parity_gdd_eom_pulsed(precision):
+    """Doubly resonant cavity with GDD on both resonant fields, an EOM, detuning, loss,
+    a pulsed pump re-read every round trip and every dispersion order."""
+    say("round trips GDD+EOM", precision)
+    ins = _stress(2048, seed=5)
+    ins["cavity"] = W.cavity(resonant=(0, 1, 1), refl=(0.0, 0.95, 0.9), delta=(0.0, 0.3, -0.2),
+                             gdd_fs2=-900.0, eom_beta=0.8, eom_fpm_thz=2.0 / 40.0)
+    nz, nrt = 12, 6
+    ref, e_ref = oracle.roundtrips(ins["crystal"], ins["cavity"], ins["fields"], ins["pump_in"], nz, nrt)
+    with _handle(ins, nz, precision) as h:
+        h.cavity_roundtrip(nrt)
+        e = h.energy_history()
+        got = h.get_fields()
+    for x in range(3):
+        assert np.max(np.abs(e[:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E[precision]
+        assert rel_l2(got[x], ref[x]) <= 10 * TOL[precision], (x, rel_l2(got[x], ref[x]))
+
+
+def test_batch_of_uneven_sizes_equals_singles_and_oracle():
+    """Instances of different nt in one handle: each equals its own single-instance run
+    bit for bit, and the oracle within the FP32 bar."""
+    say("batch uneven")
+    sizes = [16, 4096, 256, 8192, 2, 1024]
+    insts = []
+    for b, nt in enumerate(sizes):
+        ins = _stress(nt, seed=10 + b)
+        ins["cavity"] = W.cavity(resonant=(0, 1, 0), refl=(0.0, 0.8 + 0.02 * b, 0.0),
+                                 delta=(0.0, 0.1 * b, 0.0))
+        insts.append(ins)
+    nz, nrt = 8, 3
+    with B.Opo(insts, nz, precision="f32") as hb:
+        hb.cavity_roundtrip(nrt)
+        batch = [(hb.get_fields(i), hb.energy_history(i)) for i in range(len(sizes))]
+    for i, ins in enumerate(insts):
+        with _handle(ins, nz, "f32") as h:
+            h.cavity_roundtrip(nrt)
+            assert np.array_equal(batch[i][0], h.get_fields())
+            assert np.array_equal(batch[i][1], h.energy_history())
+        ref, e_ref = oracle.roundtrips(ins["crystal"], ins["cavity"], ins["fields"], ins["pump_in"],
+                                       nz, nrt)
+        for x in range(3):
+            assert rel_l2(batch[i][0][x], ref[x]) <= 10 * TOL["f32"], (i, x)
+
+
+def test_graph_replay_equals_plain_launches_and_is_deterministic():
+    w = W.config("sro_cw", nt=2048, nz=10, level=3.0)
+    outs = []
+    for graph in (True, False, True):
+        with B.from_workload(w, use_graph=graph) as h:
+            h.cavity_roundtrip(7)
+            h.cavity_roundtrip(5)
+            outs.append((h.get_fields(), h.energy_history()))
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0])
+        assert np.array_equal(o[1], outs[0][1])
+    assert outs[0][1].shape == (12, 3)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_spectrum_readout(precision):
+    ins = _stress(1 << 13, seed=7)
+    with _handle(ins, 5, precision) as h:
+        h.ssfm_propagate(5, 0.2)
+        a = h.get_fields()
+        spec = h.get_fields(domain=1)
+        t, w = h.grid()
+    for x in range(3):
+        ref = np.fft.fft(a[x])
+        assert rel_l2(spec[x], ref) <= (1e-13 if precision == "f64" else 1e-6)
+    assert np.allclose(t, W.time_grid(1 << 13, 40.0))
+    assert np.allclose(w, 2 * np.pi * np.fft.fftfreq(1 << 13, 40.0 / (1 << 13)))
+
+
+def test_nonfinite_energy_is_reported():
+    w = W.config("sro_cw", nt=256, nz=5)
+    with B.from_workload(w) as h:
+        a = h.get_fields()
+        a[1, 17] = np.nan
+        h.set_fields(a)
+        with pytest.raises(B.OpoError) as ei:
+            h.cavity_roundtrip(3)
+        assert ei.value.code == B.OPO_ENONFINITE
+        assert "round trip 0" in str(ei.value)
+
+
+def test_full_size_sro_bench_configuration():
+    """The CW SRO workload at its full size (Nt = 2^14, Nz = 100) in the launch
+    configuration the benchmark times, over three round trips from the same input."""
+    w = W.config("sro_cw")
+    nrt = 3
+    say("full-size SRO f32")
+    ref, e_ref = oracle.roundtrips(w["crystal"], w["cavity"], w["fields"], w["pump_in"], w["nz"], nrt)
+    with B.from_workload(w, precision="f32") as h:
+        h.cavity_roundtrip(nrt)
+        e = h.energy_history()
+        got = h.get_fields()
+    for x in range(3):
+        assert np.max(np.abs(e[:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E["f32"]
+        assert rel_l2(got[x], ref[x]) <= 10 * TOL["f32"], (x, rel_l2(got[x], ref[x]))
