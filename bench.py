@@ -1,0 +1,207 @@
+"""Benchmark of the OPO split-step Fourier hot path on one MI355X.
+
+A step is one cavity round trip of the whole hot path over one batch (nz
+symmetrized SSFM steps with the fused RK4 half-steps, FFTs and dispersion
+multiply, the round-trip boundary and the FP64 energy reduction, for every
+instance of the batch in the same launches) replayed from a hipGraph.
+The default workload is the batched sweep: 256 CW singly resonant OPOs with Nt
+drawn from {2^12 .. 2^16}, pump 1-6x threshold, detuning +-0.5 rad, signal
+R 0.90-0.99, Nz = 100, 500 round trips, complex64 fields with FP64 phase
+arguments and energies, seeded synthetic inputs. Variants reported beside it:
+one CW SRO at Nt = 2^14 (2000 round trips) in FP32 and in FP64.
+
+Metric: field-point-steps per second = sum over instances of Nt * Nz * round
+trips / time, with the inputs resident in HBM when the timed region starts.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2410_02532_amd import opo as B          # noqa: E402
+from paper_2410_02532_amd import workloads as W    # noqa: E402
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
+METRIC = "field-point-steps/s (Nt*Nz*round trips/s)"
+
+
+def instances_of(w):
+    return w["instances"] if "instances" in w else [w]
+
+
+def pt_steps_per_rt(w):
+    return sum(ins["crystal"]["nt"] for ins in instances_of(w)) * w["nz"]
+
+
+def timed_roundtrips(h, n_rt):
+    """Device time (HIP events on the handle's stream) and wall time of n_rt round trips."""
+    import torch
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(h.stream)
+    h.cavity_roundtrip(n_rt)
+    e1.record(h.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def run_gpu(w, steps, warmup, precision):
+    with B.from_workload(w, precision=precision) as h:
+        if warmup:
+            h.cavity_roundtrip(warmup)
+        dev_s, wall_s = timed_roundtrips(h, steps)
+    return dev_s, wall_s
+
+
+def roofline(w, precision, n_rt):
+    """Per-kernel device time from event pairs around every launch (profile option)."""
+    with B.from_workload(w, precision=precision, profile=True) as h:
+        h.cavity_roundtrip(2)            # warm up
+        before = h.kernel_times()
+        h.cavity_roundtrip(n_rt)
+        after = h.kernel_times()
+    per = {k: (after[k][0] - before[k][0], after[k][1] - before[k][1]) for k in after}
+    dom = max(("column_pass", "row_pass"), key=lambda k: per[k][0])
+    ms, launches = per[dom]
+    elem = 16 if precision == "f64" else 8
+    state = sum(3 * ins["crystal"]["nt"] * elem for ins in instances_of(w))
+    bytes_per_launch = 2 * state          # one read and one write of the three fields
+    avg_s = ms / 1e3 / launches
+    achieved = bytes_per_launch / avg_s / 1e9
+    return {
+        "bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+        "avg_launch_us": round(avg_s * 1e6, 3), "bytes_per_launch": bytes_per_launch,
+        "kernel_ms": {k: round(v[0], 3) for k, v in per.items()},
+        "launches": {k: v[1] for k, v in per.items()},
+    }
+
+
+def cpu_baseline(w, budget_s=12.0, max_rt=60):
+    """The FP64 oracle, single-threaded, on a bounded sample of the same workload.
+
+    The cost of a fixed-step round trip depends only on Nt, so the oracle runs
+    round trips of the first instance of every size present until each size
+    has had budget/len(sizes) seconds, and the batch rate is the workload's
+    total points over the time those per-size costs add up to."""
+    import oracle
+    insts = instances_of(w)
+    sizes = sorted({ins["crystal"]["nt"] for ins in insts})
+    per_size = {}
+    parts = []
+    spent = 0.0
+    for nt in sizes:
+        ins = next(i for i in insts if i["crystal"]["nt"] == nt)
+        a = ins["fields"]
+        n_rt, t = 0, 0.0
+        while n_rt < max_rt and t < budget_s / len(sizes):
+            t0 = time.perf_counter()
+            a, _ = oracle.roundtrips(ins["crystal"], ins["cavity"], a, ins["pump_in"], w["nz"], 1)
+            t += time.perf_counter() - t0
+            n_rt += 1
+        per_size[nt] = t / n_rt
+        spent += t
+        parts.append("%d x %d RT" % (nt, n_rt))
+    total_pts = sum(ins["crystal"]["nt"] for ins in insts) * w["nz"]
+    total_t = sum(per_size[ins["crystal"]["nt"]] for ins in insts)
+    return {"value": total_pts / total_t, "unit": "field-point-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%s: round trips from the seeded input of one instance per size (Nt x RT: "
+                      "%s), Nz=%d, weighted by the workload's size mix; %.1f s on one host core"
+                      % (w["name"], ", ".join(parts), w["nz"], spent)}
+
+
+def copy_calibration(nbytes=256 << 20):
+    """A plain device copy of known size, for scaling HBM counters."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print("copy calibration: %d bytes read, %d bytes written" % (nbytes, nbytes), file=sys.stderr)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed round trips")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="batched_sweep")
+    ap.add_argument("--precision", default="f32", choices=("f32", "f64"))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the single-instance FP32 and FP64 lines")
+    ap.add_argument("--no-roofline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the path has no multi-GPU mode "
+              "(batches shard by instance with no communication; see the design notes)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 1
+    if args.copy_calibration:
+        copy_calibration()
+
+    w = W.config(args.workload, precision=args.precision) if args.workload == "sro_cw" else \
+        W.config(args.workload)
+    steps = args.steps if args.steps is not None else w["n_rt"]
+    print("workload %s: %d instance(s), %d pt-steps per round trip, %d+%d round trips"
+          % (args.workload, len(instances_of(w)), pt_steps_per_rt(w), args.warmup, steps),
+          file=sys.stderr, flush=True)
+
+    dev_s, wall_s = run_gpu(w, steps, args.warmup, args.precision)
+    value = pt_steps_per_rt(w) * steps / dev_s
+    print("timed: %.4f s device, %.4f s wall -> %.4g pt-steps/s" % (dev_s, wall_s, value),
+          file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "field-point-steps/s", "n_gpus": 1,
+        "steps": steps, "warmup": args.warmup, "ms_per_step": dev_s * 1e3 / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic (seeded noise and pump, workloads module)",
+        "config": {"workload": args.workload, "instances": len(instances_of(w)),
+                   "nt": sorted({ins["crystal"]["nt"] for ins in instances_of(w)}),
+                   "nz": w["nz"], "round_trips": steps, "precision": args.precision,
+                   "graph": True, "wall_s": round(wall_s, 4)},
+    }
+    if not args.no_roofline:
+        line["roofline"] = roofline(w, args.precision, min(steps, 100))
+        print("roofline: %s" % json.dumps(line["roofline"]), file=sys.stderr, flush=True)
+
+    if not args.no_variants:
+        var = {}
+        for prec, n in (("f32", 2000), ("f64", 400)):
+            ws = W.config("sro_cw", precision=prec)
+            d, _ = run_gpu(ws, n, 10, prec)
+            var["%s_single_sro_cw_2^14" % prec] = {"value": pt_steps_per_rt(ws) * n / d,
+                                                  "round_trips": n, "ms_per_step": d * 1e3 / n}
+        line["variants"] = var
+        print("variants: %s" % json.dumps(var), file=sys.stderr, flush=True)
+
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w)
+        print("cpu baseline: %s" % json.dumps(line["cpu_baseline"]), file=sys.stderr, flush=True)
+
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -109,6 +109,11 @@ typedef struct {
     int32_t tile_b;         /* points per row-pass tile (0 = autotuned)           */
     int32_t use_graph;      /* 1 = replay each round trip from a hipGraph
                                (default), -1 = plain launches                     */
+    int32_t profile;        /* 1 = bracket every kernel launch with a pair of
+                               hipEvents on the handle's stream and accumulate
+                               per-kernel device time (plain launches instead of
+                               the graph, one stream synchronization per round
+                               trip); read with opo_kernel_times                  */
 } opo_options_t;
 
 /* Device bytes of field state for n instances (fields[i].nt) at a precision. */
@@ -161,6 +166,14 @@ int opo_get_energy_history(opo_t *h, int32_t inst, double *out, int32_t capacity
 
 /* Time samples t_j [ps] and angular frequencies w_k [rad/ps] of an instance. */
 int opo_get_grid(opo_t *h, int32_t inst, double *t, double *omega);
+
+/* Kernel classes timed by the profile option. */
+enum { OPO_K_COLUMN = 0, OPO_K_ROW = 1, OPO_K_ENERGY = 2, OPO_K_CLASSES = 3 };
+
+/* Device time [ms] summed over launches, and launch counts, of each kernel
+ * class since the handle was created (profile option), OPO_K_CLASSES
+ * entries each; zeros without the profile option. */
+int opo_kernel_times(opo_t *h, double *ms, int64_t *launches);
 
 /* Number of instances, and the current z [mm] of the handle. */
 int opo_info(opo_t *h, int32_t *n_instances, double *z_mm);

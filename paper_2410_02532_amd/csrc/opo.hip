@@ -103,6 +103,13 @@ struct opo_s {
     hipGraphExec_t graph = nullptr;
     void *scratch = nullptr;         // spectrum read-out
     std::vector<double> t_window;    // T of every instance [ps]
+    // profile option: event pairs of the launches since the last collection
+    bool profile = false;
+    std::vector<hipEvent_t> events;
+    std::vector<int> ev_class;
+    size_t ev_used = 0;
+    double k_ms[OPO_K_CLASSES] = {0.0, 0.0, 0.0};
+    long long k_count[OPO_K_CLASSES] = {0, 0, 0};
 };
 
 namespace opo {
@@ -235,6 +242,8 @@ static void release(opo_t *h)
                     h->d_partial, h->d_hist, h->d_counter, h->scratch};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
+    for (hipEvent_t e : h->events)
+        if (e) (void)hipEventDestroy(e);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
     {
         std::lock_guard<std::mutex> lk(g_live_mu);
@@ -256,19 +265,61 @@ template <typename R> static StepArgs<R> base_args(opo_t *h, void *state)
     return a;
 }
 
+// profile option: open an event pair around the next launch of class k
+static void prof_begin(opo_t *h, int k)
+{
+    if (!h->profile) return;
+    if (h->ev_used + 2 > h->events.size()) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        h->events.push_back(e0);
+        h->events.push_back(e1);
+        h->ev_class.push_back(k);
+    }
+    h->ev_class[h->ev_used / 2] = k;
+    (void)hipEventRecord(h->events[h->ev_used], h->stream);
+}
+
+static void prof_end(opo_t *h)
+{
+    if (!h->profile) return;
+    (void)hipEventRecord(h->events[h->ev_used + 1], h->stream);
+    h->ev_used += 2;
+}
+
+// profile option: wait for the recorded launches and add up the times of the
+// first `used` events
+static int prof_collect(opo_t *h, size_t used)
+{
+    if (!h->profile || used == 0) return OPO_OK;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (size_t i = 0; i < used; i += 2) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->events[i], h->events[i + 1]));
+        h->k_ms[h->ev_class[i / 2]] += ms;
+        h->k_count[h->ev_class[i / 2]] += 1;
+    }
+    return OPO_OK;
+}
+
 template <typename R> static void launch_a(opo_t *h, StepArgs<R> a, int flags, int step)
 {
     a.tile_inst = h->d_tile_a;
     a.flags = flags;
     a.step = step;
+    prof_begin(h, OPO_K_COLUMN);
     column_pass<R><<<h->tiles_a, kThreads, h->lds_a, h->stream>>>(a);
+    prof_end(h);
 }
 
 template <typename R> static void launch_b(opo_t *h, StepArgs<R> a, int flags)
 {
     a.tile_inst = h->d_tile_b;
     a.flags = flags;
+    prof_begin(h, OPO_K_ROW);
     row_pass<R><<<h->tiles_b, kThreads, h->lds_b, h->stream>>>(a);
+    prof_end(h);
 }
 
 // One crystal pass of nz steps. `first` flags are OR-ed into the opening
@@ -298,8 +349,10 @@ template <typename R> static void enqueue_roundtrip(opo_t *h)
     } else {
         enqueue_pass<R>(h, a, h->nz, A_REFRESH, A_ENERGY | A_MIRROR | eom);
     }
+    prof_begin(h, OPO_K_ENERGY);
     energy_reduce<<<1, kThreads, 0, h->stream>>>(h->d_inst, h->n_inst, h->d_partial, h->d_hist,
                                                  h->d_counter, kHistChunk);
+    prof_end(h);
 }
 
 template <typename R> static int setup_kernels(opo_t *h)
@@ -316,6 +369,9 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
 {
     opo_options_t opt{};
     if (opt_in) opt = *opt_in;
+    // HIP cannot time events recorded inside a captured graph: the profile
+    // option runs the round trip as plain launches
+    if (opt.profile) opt.use_graph = -1;
     if (opt.precision != OPO_F32 && opt.precision != OPO_F64)
         return fail(OPO_EINVAL, "precision must be OPO_F32 or OPO_F64");
     int rc = validate(n, f, c, k, opt.precision);
@@ -338,6 +394,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     h->nz = c[0].nz;
     h->elem = opt.precision == OPO_F64 ? 16 : 8;
     h->use_graph = opt.use_graph >= 0 ? 1 : 0;
+    h->profile = opt.profile != 0;
     const int tile_a = opt.tile_a > 0 ? opt.tile_a : default_tile_a(opt.precision);
     const int tile_b = opt.tile_b > 0 ? opt.tile_b : default_tile_b(opt.precision);
 
@@ -537,7 +594,9 @@ template <typename R> static int propagate_impl(opo_t *h, int nz, double dz)
     enqueue_pass<R>(h, a, nz, 0, 0);
     HIP_TRY(hipGetLastError());
     h->z += nz * dz;
-    return OPO_OK;
+    const size_t used = h->ev_used;
+    h->ev_used = 0;
+    return prof_collect(h, used);
 }
 
 template <typename R> static int roundtrip_impl(opo_t *h, int n_rt)
@@ -566,6 +625,10 @@ template <typename R> static int roundtrip_impl(opo_t *h, int n_rt)
                 HIP_TRY(hipGraphLaunch(h->graph, h->stream));
             } else {
                 enqueue_roundtrip<R>(h);
+                const size_t used = h->ev_used;
+                h->ev_used = 0;
+                int prc = prof_collect(h, used);
+                if (prc) return prc;
             }
         }
         HIP_TRY(hipGetLastError());
@@ -746,6 +809,17 @@ int opo_get_grid(opo_t *h, int32_t inst, double *t, double *omega)
     for (int j = 0; j < nt; ++j) {
         if (t) t[j] = -0.5 * T + j * (T / nt);
         if (omega) omega[j] = kTwoPi * (j < nt / 2 ? j : j - nt) / T;
+    }
+    return OPO_OK;
+}
+
+int opo_kernel_times(opo_t *h, double *ms, int64_t *launches)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    for (int k = 0; k < OPO_K_CLASSES; ++k) {
+        if (ms) ms[k] = h->k_ms[k];
+        if (launches) launches[k] = h->k_count[k];
     }
     return OPO_OK;
 }

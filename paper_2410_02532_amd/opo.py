@@ -19,7 +19,8 @@ STATUS = {0: "OPO_OK", -1: "OPO_EINVAL", -2: "OPO_ENOMEM", -3: "OPO_EDEVICE",
 
 EXPORTS = ("opo_state_bytes", "opo_init", "opo_init_batch", "ssfm_propagate", "cavity_roundtrip",
            "opo_sync", "opo_get_fields", "opo_set_fields", "opo_get_energy_history",
-           "opo_get_grid", "opo_info", "opo_destroy", "opo_last_error")
+           "opo_get_grid", "opo_kernel_times", "opo_info", "opo_destroy", "opo_last_error")
+KERNEL_CLASSES = ("column_pass", "row_pass", "energy_reduce")
 
 _d3 = ctypes.c_double * 3
 _i3 = ctypes.c_int32 * 3
@@ -49,7 +50,8 @@ class OptionsT(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("state", ctypes.c_void_p),
                 ("state_bytes", ctypes.c_uint64), ("tile_a", ctypes.c_int32),
-                ("tile_b", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("tile_b", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("profile", ctypes.c_int32)]
 
 
 class OpoError(RuntimeError):
@@ -85,12 +87,13 @@ def load():
     lib.opo_get_energy_history.argtypes = [P, I, P, I, ctypes.POINTER(I)]
     lib.opo_get_grid.argtypes = [P, I, P, P]
     lib.opo_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(D)]
+    lib.opo_kernel_times.argtypes = [P, P, P]
     lib.opo_destroy.argtypes = [P]
     lib.opo_last_error.argtypes = []
     lib.opo_last_error.restype = ctypes.c_char_p
     for name in ("opo_init", "opo_init_batch", "ssfm_propagate", "cavity_roundtrip", "opo_sync",
                  "opo_get_fields", "opo_set_fields", "opo_get_energy_history", "opo_get_grid",
-                 "opo_info", "opo_destroy"):
+                 "opo_kernel_times", "opo_info", "opo_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -161,7 +164,7 @@ class Opo:
     """
 
     def __init__(self, instances, nz, precision="f32", device=0, tile_a=0, tile_b=0,
-                 use_graph=True):
+                 use_graph=True, profile=False):
         import torch
         lib = load()
         self._lib = lib
@@ -177,7 +180,8 @@ class Opo:
         opt = OptionsT(precision=self.precision, device=device,
                        stream=ctypes.c_void_p(self._stream.cuda_stream),
                        state=ctypes.c_void_p(self._state.data_ptr()), state_bytes=nbytes,
-                       tile_a=int(tile_a), tile_b=int(tile_b), use_graph=1 if use_graph else -1)
+                       tile_a=int(tile_a), tile_b=int(tile_b), use_graph=1 if use_graph else -1,
+                       profile=1 if profile else 0)
         h = ctypes.c_void_p()
         _check(lib.opo_init_batch(ctypes.byref(h), self.n, fields, crystals, cavities,
                                   ctypes.byref(opt)))
@@ -224,6 +228,17 @@ class Opo:
         t, w = np.empty(nt), np.empty(nt)
         _check(self._lib.opo_get_grid(self.h, inst, t.ctypes.data, w.ctypes.data))
         return t, w
+
+    def kernel_times(self):
+        """{kernel class: (total device ms, launches)} under the profile option."""
+        ms = np.zeros(3)
+        n = np.zeros(3, dtype=np.int64)
+        _check(self._lib.opo_kernel_times(self.h, ms.ctypes.data, n.ctypes.data))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    @property
+    def stream(self):
+        return self._stream
 
     def info(self):
         n, z = ctypes.c_int32(), ctypes.c_double()
