@@ -1,15 +1,21 @@
-// fft_tile.h -- LDS-staged Stockham FFT over a batch of short transforms held
-// by one workgroup, plus the complex helpers the kernels share.
+// fft_tile.h -- register-resident Stockham FFT over short transforms held by a
+// workgroup, plus the complex helpers the kernels share.
 //
-// A tile keeps `count` transforms of length m (a power of two) in LDS; element
-// n of transform t sits at lds_index(t*m + n). Each stage of radix R (8, 4 or
-// 2) reads R values per butterfly at stride m/R, twiddles them, applies the
-// R-point DFT in registers and writes them back at stride p in the
-// self-sorting (Stockham) order, so the result comes out in natural order
-// without a bit-reversal pass. The stage is done in place: every thread loads
-// all of its butterflies into registers, the workgroup synchronizes, then
-// every thread writes. Twiddles of the butterflies come from one table
-// e^{-2 pi i q/TWL}, q < TWL, built on the host in FP64.
+// A transform of length N is spread over N/PF threads; thread t of the
+// transform keeps the PF samples at positions t + m*(N/PF), m < PF, in
+// registers. Each Stockham stage of radix RS (8, 4 or 2, dividing PF) runs
+// PF/RS butterflies per thread whose inputs are exactly those register
+// samples: butterfly u of thread t has index i = t + u*(N/PF) and reads
+// positions i + r*(N/RS). The stage twiddles by w^{r k} (k = i mod P, P the
+// product of the earlier radices, w = e^{-+2 pi i/(P RS)}), applies the
+// RS-point DFT and writes the self-sorting positions j + r*P,
+// j = (i - k)*RS + k. Between stages the samples go through LDS (one write,
+// one read back of the thread's own positions). In the last stage P = N/RS,
+// so j = i and the outputs land on the thread's own positions: the result
+// comes back in natural order in registers, with no LDS traffic. Twiddles
+// come from one table e^{-2 pi i q/kTwL} built on the host in FP64 (held as
+// compensated FP32 pairs in the FP32 path), and are loaded once per stage and
+// reused for every transform the thread owns.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -17,9 +23,6 @@ namespace opo {
 
 constexpr int kThreads = 256;   // threads per workgroup of every tile kernel
 constexpr int kTwL = 8192;      // length of the butterfly twiddle table
-// Tile points per thread (register budget of a stage): a tile holds at most
-// kThreads * max_pts<R>() points.
-template <typename R> __host__ __device__ constexpr int max_pts() { return sizeof(R) == 4 ? 16 : 8; }
 
 template <typename R> struct cplx_of;
 template <> struct cplx_of<float> { using type = float2; };
@@ -46,18 +49,81 @@ template <typename V> __device__ __forceinline__ V cmulc(V a, V b)
 }
 template <typename V> __device__ __forceinline__ V conjv(V a) { return mk<V>(a.x, -a.y); }
 template <typename V, typename S> __device__ __forceinline__ V cscale(V a, S s) { return mk<V>(a.x * s, a.y * s); }
-// multiply by -i*dir... : rot(a, dir) = a * (dir * i)
+// a * (DIR i): DIR = +1 multiplies by i, DIR = -1 by -i
 template <int DIR, typename V> __device__ __forceinline__ V rot90(V a)
 {
-    // DIR = +1: a * i ; DIR = -1: a * (-i)
     return DIR > 0 ? mk<V>(-a.y, a.x) : mk<V>(a.y, -a.x);
+}
+
+// A unit-modulus factor (twiddle, propagator, mirror) carried with FP64
+// accuracy. In the FP32 path it is the FP32 value hi nearest to the FP64
+// factor plus the FP32 remainder lo, and x*(hi + lo) is formed with the small
+// product first: the factor's own rounding then no longer biases |x| by the
+// same amount at every step (a per-frequency error that a plain FP32 factor
+// would compound over 10^5 steps). In the FP64 path it is the factor itself.
+template <typename R> struct Phasor;
+template <> struct Phasor<float> {
+    float2 hi, lo;
+};
+template <> struct Phasor<double> {
+    double2 hi;
+};
+
+template <typename R> __host__ __device__ __forceinline__ Phasor<R> make_phasor(double re, double im);
+template <> __host__ __device__ __forceinline__ Phasor<float> make_phasor<float>(double re, double im)
+{
+    Phasor<float> p;
+    p.hi.x = static_cast<float>(re);
+    p.hi.y = static_cast<float>(im);
+    p.lo.x = static_cast<float>(re - static_cast<double>(p.hi.x));
+    p.lo.y = static_cast<float>(im - static_cast<double>(p.hi.y));
+    return p;
+}
+template <> __host__ __device__ __forceinline__ Phasor<double> make_phasor<double>(double re, double im)
+{
+    Phasor<double> p;
+    p.hi.x = re;
+    p.hi.y = im;
+    return p;
+}
+
+// x * w (CONJ = false) or x * conj(w) (CONJ = true).
+template <bool CONJ = false>
+__device__ __forceinline__ float2 pmul(float2 x, const Phasor<float> &w)
+{
+    const float hy = CONJ ? -w.hi.y : w.hi.y, ly = CONJ ? -w.lo.y : w.lo.y;
+    float re = x.x * w.lo.x - x.y * ly;
+    float im = x.x * ly + x.y * w.lo.x;
+    re = fmaf(x.x, w.hi.x, re);
+    re = fmaf(-x.y, hy, re);
+    im = fmaf(x.x, hy, im);
+    im = fmaf(x.y, w.hi.x, im);
+    return make_float2(re, im);
+}
+template <bool CONJ = false>
+__device__ __forceinline__ double2 pmul(double2 x, const Phasor<double> &w)
+{
+    return CONJ ? cmulc(x, w.hi) : cmul(x, w.hi);
 }
 
 // LDS padding: one spare element every 2^shift elements spreads strided
 // accesses over the banks (8-byte elements: every 16, 16-byte: every 8).
-template <typename R> struct lds_pad { static constexpr int shift = sizeof(R) == 4 ? 4 : 3; };
-template <typename R> __device__ __forceinline__ int lds_index(int e) { return e + (e >> lds_pad<R>::shift); }
-template <typename R> __host__ __device__ constexpr int lds_elems(int n) { return n + (n >> (sizeof(R) == 4 ? 4 : 3)) + 1; }
+#ifndef OPO_LDS_SHIFT_F32
+#define OPO_LDS_SHIFT_F32 5
+#endif
+template <typename R> __host__ __device__ constexpr int lds_shift() { return sizeof(R) == 4 ? OPO_LDS_SHIFT_F32 : 3; }
+template <typename R> __device__ __forceinline__ int lds_index(int e) { return e + (e >> lds_shift<R>()); }
+template <typename R> __host__ __device__ constexpr int lds_elems(int n) { return n + (n >> lds_shift<R>()) + 1; }
+
+// Workgroup barrier that orders LDS accesses only: global loads still in
+// flight (a prefetch of the next tile) are not waited for, unlike
+// __syncthreads().
+__device__ __forceinline__ void lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // R-point DFT in registers, y_k = sum_j x_j e^{DIR 2 pi i jk/R}.
 template <int DIR, typename V> __device__ __forceinline__ void dft2(V *x)
@@ -77,18 +143,27 @@ template <int DIR, typename V> __device__ __forceinline__ void dft4(V *x)
     x[3] = csub(b, d);
 }
 
+// s * 1/sqrt(2): in FP32 with the constant split in hi + lo, so that the
+// eighth-root twiddles keep unit modulus to FP64 accuracy (a plain FP32
+// 1/sqrt(2) has |w|^2 = 1 - 2.7e-8, the same at every step).
+__device__ __forceinline__ float mul_rsqrt2(float a)
+{
+    const float hi = 0.70710677f;                 // nearest FP32 to 1/sqrt(2)
+    const float lo = 1.21016175e-08f;             // 1/sqrt(2) - hi
+    return fmaf(a, hi, a * lo);
+}
+__device__ __forceinline__ double mul_rsqrt2(double a) { return a * 0.70710678118654752440; }
+
 template <int DIR, typename V> __device__ __forceinline__ void dft8(V *x)
 {
-    using S = decltype(V::x);
-    const S h = S(0.70710678118654752440);
     V e[4] = {x[0], x[2], x[4], x[6]};
     V o[4] = {x[1], x[3], x[5], x[7]};
     dft4<DIR>(e);
     dft4<DIR>(o);
     // w^k = e^{DIR 2 pi i k/8}
-    V o1 = mk<V>(h * (o[1].x - DIR * o[1].y), h * (o[1].y + DIR * o[1].x));
+    V o1 = mk<V>(mul_rsqrt2(o[1].x - DIR * o[1].y), mul_rsqrt2(o[1].y + DIR * o[1].x));
     V o2 = rot90<DIR>(o[2]);
-    V o3 = mk<V>(h * (-o[3].x - DIR * o[3].y), h * (-o[3].y + DIR * o[3].x));
+    V o3 = mk<V>(mul_rsqrt2(-o[3].x - DIR * o[3].y), mul_rsqrt2(-o[3].y + DIR * o[3].x));
     x[0] = cadd(e[0], o[0]);
     x[4] = csub(e[0], o[0]);
     x[1] = cadd(e[1], o1);
@@ -106,70 +181,92 @@ template <int RAD, int DIR, typename V> __device__ __forceinline__ void dft(V *x
     else dft2<DIR>(x);
 }
 
-// One Stockham stage of radix RAD over `count` transforms of length m whose
-// sub-transforms of length p are already done.
-template <typename R, int DIR, int RAD>
-__device__ __forceinline__ void fft_stage(cplx<R> *s, int count, int log2m, int p,
-                                          const cplx<R> *__restrict__ tw)
+// Radix of the stage that follows sub-transforms of length P.
+template <int N, int PF, int P> __host__ __device__ constexpr int stage_radix()
 {
-    using V = cplx<R>;
-    constexpr int NB = max_pts<R>() / RAD;   // butterflies a thread may own
-    const int m = 1 << log2m;
-    const int nb = m / RAD;             // butterflies per transform
-    const int lognb = log2m - (RAD == 8 ? 3 : RAD == 4 ? 2 : 1);
-    const int total = count << lognb;
-    const int tw_stride = kTwL / (p * RAD);
-    V v[NB][RAD];
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-        const int b = threadIdx.x + u * kThreads;
-        if (b < total) {
-            const int t = b >> lognb, i = b & (nb - 1);
-            const int base = t << log2m;
-#pragma unroll
-            for (int r = 0; r < RAD; ++r)
-                v[u][r] = s[lds_index<R>(base + i + r * nb)];
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < NB; ++u) {
-        const int b = threadIdx.x + u * kThreads;
-        if (b < total) {
-            const int t = b >> lognb, i = b & (nb - 1);
-            const int base = t << log2m;
-            const int k = i & (p - 1);
-            if (p > 1) {
-#pragma unroll
-                for (int r = 1; r < RAD; ++r) {
-                    V w = tw[r * k * tw_stride];
-                    if (DIR > 0) w = conjv(w);
-                    v[u][r] = cmul(v[u][r], w);
-                }
-            }
-            dft<RAD, DIR>(v[u]);
-            const int j = (i - k) * RAD + k;
-#pragma unroll
-            for (int r = 0; r < RAD; ++r)
-                s[lds_index<R>(base + j + r * p)] = v[u][r];
-        }
-    }
-    __syncthreads();
+    return (N / P >= 8 && PF % 8 == 0) ? 8 : (N / P >= 4 && PF % 4 == 0) ? 4 : 2;
 }
 
-// Unnormalized DFT of `count` transforms of length 2^log2m in LDS, DIR = -1
-// forward (e^{-...}), +1 inverse (e^{+...}). Expects a synchronized tile.
-template <typename R, int DIR>
-__device__ void tile_fft(cplx<R> *s, int count, int log2m, const cplx<R> *__restrict__ tw)
+// One stage over NTR transforms held by this thread. Position n of transform
+// tr lives at LDS element base[tr] + n*LS; t is the thread's index in its
+// transform.
+template <typename R, int N, int PF, int NTR, int DIR, int LS, int RS, int P>
+__device__ __forceinline__ void reg_stage(cplx<R> (&v)[NTR][PF], cplx<R> *lds, const int (&base)[NTR],
+                                          int t, const Phasor<R> *__restrict__ tw)
 {
-    int p = 1, left = log2m;
-    while (left >= 3) {
-        fft_stage<R, DIR, 8>(s, count, log2m, p, tw);
-        p <<= 3;
-        left -= 3;
+    using V = cplx<R>;
+    constexpr int NBT = PF / RS;       // butterflies per thread and transform
+    constexpr int STRIDE = N / PF;     // distance between a thread's samples
+    constexpr bool LAST = P * RS == N;
+    Phasor<R> w[NBT][RS];
+    if constexpr (P > 1) {
+#pragma unroll
+        for (int u = 0; u < NBT; ++u) {
+            const int k = (t + u * STRIDE) & (P - 1);
+#pragma unroll
+            for (int r = 1; r < RS; ++r)
+                w[u][r] = tw[r * k * (kTwL / (P * RS))];
+        }
     }
-    if (left == 2) fft_stage<R, DIR, 4>(s, count, log2m, p, tw);
-    else if (left == 1) fft_stage<R, DIR, 2>(s, count, log2m, p, tw);
+#pragma unroll
+    for (int tr = 0; tr < NTR; ++tr) {
+#pragma unroll
+        for (int u = 0; u < NBT; ++u) {
+            V x[RS];
+#pragma unroll
+            for (int r = 0; r < RS; ++r)
+                x[r] = v[tr][u + r * NBT];
+            if constexpr (P > 1) {
+#pragma unroll
+                for (int r = 1; r < RS; ++r)
+                    x[r] = pmul<(DIR > 0)>(x[r], w[u][r]);
+            }
+            dft<RS, DIR>(x);
+            if constexpr (LAST) {
+#pragma unroll
+                for (int r = 0; r < RS; ++r)
+                    v[tr][u + r * NBT] = x[r];
+            } else {
+                const int i = t + u * STRIDE;
+                const int k = i & (P - 1);
+                const int j = (i - k) * RS + k;
+#pragma unroll
+                for (int r = 0; r < RS; ++r)
+                    lds[lds_index<R>(base[tr] + (j + r * P) * LS)] = x[r];
+            }
+        }
+    }
+    if constexpr (!LAST) {
+        lds_sync();
+#pragma unroll
+        for (int tr = 0; tr < NTR; ++tr)
+#pragma unroll
+            for (int m = 0; m < PF; ++m)
+                v[tr][m] = lds[lds_index<R>(base[tr] + (t + m * STRIDE) * LS)];
+        lds_sync();
+    }
+}
+
+template <typename R, int N, int PF, int NTR, int DIR, int LS, int P>
+__device__ __forceinline__ void reg_fft_from(cplx<R> (&v)[NTR][PF], cplx<R> *lds, const int (&base)[NTR],
+                                             int t, const Phasor<R> *__restrict__ tw)
+{
+    if constexpr (P < N) {
+        constexpr int RS = stage_radix<N, PF, P>();
+        reg_stage<R, N, PF, NTR, DIR, LS, RS, P>(v, lds, base, t, tw);
+        reg_fft_from<R, N, PF, NTR, DIR, LS, P * RS>(v, lds, base, t, tw);
+    }
+}
+
+// Unnormalized DFT (DIR -1: e^{-...}, +1: e^{+...}) of NTR transforms of
+// length N. On entry and on exit v[tr][m] is sample t + m*(N/PF). Every
+// thread of the workgroup must call it (it synchronizes the workgroup when
+// N > PF). LS is the LDS element stride between consecutive positions.
+template <typename R, int N, int PF, int NTR, int DIR, int LS>
+__device__ __forceinline__ void reg_fft(cplx<R> (&v)[NTR][PF], cplx<R> *lds, const int (&base)[NTR], int t,
+                                        const Phasor<R> *__restrict__ tw)
+{
+    reg_fft_from<R, N, PF, NTR, DIR, LS, 1>(v, lds, base, t, tw);
 }
 
 } // namespace opo

@@ -36,7 +36,7 @@ static constexpr double kTwoPi = 6.283185307179586476925286766559;
 static constexpr double kPi = 3.1415926535897932384626433832795;
 
 struct Plan {
-    int log2n1, log2n2, log2cols, log2rows;
+    int log2n1, log2n2, cols, rows;
 };
 
 static int ilog2(long long v)
@@ -46,28 +46,58 @@ static int ilog2(long long v)
     return l;
 }
 
-// Default tile sizes (points per tile) before any autotuning.
-static int default_tile_a(int precision) { return precision == OPO_F64 ? 768 : 1536; }
-static int default_tile_b(int precision) { return precision == OPO_F64 ? 512 : 1024; }
-
-static Plan make_plan(int nt, int precision, int tile_a, int tile_b)
+// Four-step split nt = n1 * n2: balanced up to 2^12, then columns of 64
+// (short column transforms keep three fields of 128-byte column groups in
+// registers) and rows up to the longest row kernel, then longer columns.
+static Plan make_plan(int nt, int precision)
 {
     Plan p;
     const int l = ilog2(nt);
-    p.log2n2 = std::min(l / 2, 8);
+    const int max_ln1 = precision == OPO_F64 ? kMaxLog2N1<double> : kMaxLog2N1<float>;
+    if (l <= 12) p.log2n2 = l / 2;
+    else p.log2n2 = std::max(6, l - max_ln1);
     p.log2n1 = l - p.log2n2;
-    const int maxpts = kThreads * (precision == OPO_F64 ? max_pts<double>() : max_pts<float>());
-    // columns per column tile: 3 * cols * n2 points, within [1, n1]
-    int ca = std::max(1, std::min(tile_a, maxpts) / (3 << p.log2n2));
-    int lc = 0;
-    while ((2 << lc) <= ca) ++lc;
-    p.log2cols = std::min(lc, p.log2n1);
-    while (p.log2cols > 0 && (3 << (p.log2n2 + p.log2cols)) > maxpts) --p.log2cols;
-    int rb = std::max(1, std::min(tile_b, maxpts) >> p.log2n1);
-    int lr = 0;
-    while ((2 << lr) <= rb) ++lr;
-    p.log2rows = std::min(lr, p.log2n2);
+    p.cols = precision == OPO_F64 ? col_cols<double>(p.log2n2) : col_cols<float>(p.log2n2);
+    p.rows = precision == OPO_F64 ? row_rows<double>(p.log2n1) : row_rows<float>(p.log2n1);
     return p;
+}
+
+// A run of tiles that share one kernel instantiation.
+struct Group {
+    int ln;       // index of the size range
+    int tile0;    // first tile
+    int count;    // tiles
+};
+
+// Index of the size range (kColRanges / kRowRanges) that contains ln.
+template <size_t K> static int range_of(const int (&ranges)[K][2], int ln)
+{
+    for (size_t i = 0; i < K; ++i)
+        if (ln >= ranges[i][0] && ln <= ranges[i][1]) return static_cast<int>(i);
+    return -1;
+}
+
+template <typename R> static const void *column_fn(int range)
+{
+    switch (range) {
+    case 0: return reinterpret_cast<const void *>(&column_pass<R, kColRanges[0][0], kColRanges[0][1]>);
+    case 1: return reinterpret_cast<const void *>(&column_pass<R, kColRanges[1][0], kColRanges[1][1]>);
+    case 2: return reinterpret_cast<const void *>(&column_pass<R, kColRanges[2][0], kColRanges[2][1]>);
+    default: return nullptr;
+    }
+}
+
+template <typename R> static const void *row_fn(int range)
+{
+    switch (range) {
+    case 0: return reinterpret_cast<const void *>(&row_pass<R, kRowRanges[0][0], kRowRanges[0][1]>);
+    case 1: return reinterpret_cast<const void *>(&row_pass<R, kRowRanges[1][0], kRowRanges[1][1]>);
+    case 2:
+        if constexpr (kMaxLog2N1<R> >= kRowRanges[2][0])
+            return reinterpret_cast<const void *>(&row_pass<R, kRowRanges[2][0], kRowRanges[2][1]>);
+        return nullptr;
+    default: return nullptr;
+    }
 }
 
 } // namespace opo
@@ -89,8 +119,12 @@ struct opo_s {
     std::vector<InstDesc> inst;
     InstDesc *d_inst = nullptr;
     int tiles_a = 0, tiles_b = 0;
+    std::vector<Group> groups_a, groups_b;   // tiles of one transform length
     int *d_tile_a = nullptr, *d_tile_b = nullptr;
     void *d_tw = nullptr, *d_tw4 = nullptr;
+    void *d_disp = nullptr;          // linear-propagator tables, one per distinct crystal/grid
+    std::vector<int> disp_owner;     // instance whose parameters define each table
+    double disp_mode = -1.0;         // step the tables hold: > 0 explicit dz, 0 = L/nz, < 0 none
     double *d_partial = nullptr;
     double *d_hist = nullptr;
     int *d_counter = nullptr;
@@ -196,15 +230,25 @@ static void build_twiddles_rows(std::vector<double> &re, std::vector<double> &im
     }
 }
 
-template <typename R> static void upload_cplx(void *dst, const std::vector<double> &re,
-                                              const std::vector<double> &im, hipStream_t st)
+// Unit-modulus factors computed in FP64, stored as Phasor<R> (compensated
+// FP32 pairs, or FP64).
+template <typename R> static void upload_phasors(void *dst, const std::vector<double> &re,
+                                                 const std::vector<double> &im, hipStream_t st)
 {
-    std::vector<R> buf(2 * re.size());
-    for (size_t i = 0; i < re.size(); ++i) {
-        buf[2 * i] = static_cast<R>(re[i]);
-        buf[2 * i + 1] = static_cast<R>(im[i]);
-    }
-    (void)hipMemcpyAsync(dst, buf.data(), buf.size() * sizeof(R), hipMemcpyHostToDevice, st);
+    std::vector<Phasor<R>> buf(re.size());
+    for (size_t i = 0; i < re.size(); ++i)
+        buf[i] = make_phasor<R>(re[i], im[i]);
+    (void)hipMemcpyAsync(dst, buf.data(), buf.size() * sizeof(Phasor<R>), hipMemcpyHostToDevice, st);
+    (void)hipStreamSynchronize(st);
+}
+
+static void upload_double2(void *dst, const std::vector<double> &re, const std::vector<double> &im,
+                           hipStream_t st)
+{
+    std::vector<double2> buf(re.size());
+    for (size_t i = 0; i < re.size(); ++i)
+        buf[i] = make_double2(re[i], im[i]);
+    (void)hipMemcpyAsync(dst, buf.data(), buf.size() * sizeof(double2), hipMemcpyHostToDevice, st);
     (void)hipStreamSynchronize(st);
 }
 
@@ -238,7 +282,7 @@ static void release(opo_t *h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->own_state && h->state) (void)hipFree(h->state);
-    void *bufs[] = {h->pump, h->d_inst, h->d_tile_a, h->d_tile_b, h->d_tw, h->d_tw4,
+    void *bufs[] = {h->pump, h->d_inst, h->d_tile_a, h->d_tile_b, h->d_tw, h->d_tw4, h->d_disp,
                     h->d_partial, h->d_hist, h->d_counter, h->scratch};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -258,8 +302,9 @@ template <typename R> static StepArgs<R> base_args(opo_t *h, void *state)
     a.inst = h->d_inst;
     a.state = static_cast<cplx<R> *>(state);
     a.pump = static_cast<const cplx<R> *>(h->pump);
-    a.tw = static_cast<const cplx<R> *>(h->d_tw);
-    a.tw4 = static_cast<const cplx<R> *>(h->d_tw4);
+    a.tw = static_cast<const Phasor<R> *>(h->d_tw);
+    a.tw4 = static_cast<const double2 *>(h->d_tw4);
+    a.disp = static_cast<const Phasor<R> *>(h->d_disp);
     a.partial = h->d_partial;
     a.nz = h->nz;
     return a;
@@ -309,7 +354,12 @@ template <typename R> static void launch_a(opo_t *h, StepArgs<R> a, int flags, i
     a.flags = flags;
     a.step = step;
     prof_begin(h, OPO_K_COLUMN);
-    column_pass<R><<<h->tiles_a, kThreads, h->lds_a, h->stream>>>(a);
+    for (const Group &g : h->groups_a) {
+        a.tile0 = g.tile0;
+        a.tile_count = g.count;
+        void *args[] = {&a};
+        (void)hipLaunchKernel(column_fn<R>(g.ln), dim3(g.count), dim3(kThreads), args, h->lds_a, h->stream);
+    }
     prof_end(h);
 }
 
@@ -318,7 +368,12 @@ template <typename R> static void launch_b(opo_t *h, StepArgs<R> a, int flags)
     a.tile_inst = h->d_tile_b;
     a.flags = flags;
     prof_begin(h, OPO_K_ROW);
-    row_pass<R><<<h->tiles_b, kThreads, h->lds_b, h->stream>>>(a);
+    for (const Group &g : h->groups_b) {
+        a.tile0 = g.tile0;
+        a.tile_count = g.count;
+        void *args[] = {&a};
+        (void)hipLaunchKernel(row_fn<R>(g.ln), dim3(g.count), dim3(kThreads), args, h->lds_b, h->stream);
+    }
     prof_end(h);
 }
 
@@ -357,10 +412,16 @@ template <typename R> static void enqueue_roundtrip(opo_t *h)
 
 template <typename R> static int setup_kernels(opo_t *h)
 {
-    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&column_pass<R>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(h->lds_a)));
-    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&row_pass<R>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(h->lds_b)));
+    for (const Group &g : h->groups_a) {
+        if (!column_fn<R>(g.ln)) return fail(OPO_EINVAL, "internal: no column kernel for this size");
+        HIP_TRY(hipFuncSetAttribute(column_fn<R>(g.ln), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(h->lds_a)));
+    }
+    for (const Group &g : h->groups_b) {
+        if (!row_fn<R>(g.ln)) return fail(OPO_EINVAL, "internal: no row kernel for this size");
+        HIP_TRY(hipFuncSetAttribute(row_fn<R>(g.ln), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(h->lds_b)));
+    }
     return OPO_OK;
 }
 
@@ -395,8 +456,6 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     h->elem = opt.precision == OPO_F64 ? 16 : 8;
     h->use_graph = opt.use_graph >= 0 ? 1 : 0;
     h->profile = opt.profile != 0;
-    const int tile_a = opt.tile_a > 0 ? opt.tile_a : default_tile_a(opt.precision);
-    const int tile_b = opt.tile_b > 0 ? opt.tile_b : default_tile_b(opt.precision);
 
     auto bail = [&](int code) {
         release(h);
@@ -421,15 +480,15 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     for (int i = 0; i < n; ++i) {
         InstDesc &d = h->inst[i];
         std::memset(&d, 0, sizeof(d));
-        const Plan p = make_plan(f[i].nt, opt.precision, tile_a, tile_b);
+        const Plan p = make_plan(f[i].nt, opt.precision);
         d.nt = f[i].nt;
         d.log2nt = ilog2(d.nt);
         d.n1 = 1 << p.log2n1;
         d.log2n1 = p.log2n1;
         d.n2 = 1 << p.log2n2;
         d.log2n2 = p.log2n2;
-        d.log2cols = p.log2cols;
-        d.log2rows = p.log2rows;
+        d.cols = p.cols;
+        d.rows = p.rows;
         d.off = off;
         off += 3LL * d.nt;
         d.pump_off = -1;
@@ -437,24 +496,15 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
             d.pump_off = pump_elems;
             pump_elems += d.nt;
         }
-        d.tile_a0 = h->tiles_a;
-        d.tiles_a = d.n1 >> p.log2cols;
-        h->tiles_a += d.tiles_a;
-        for (int t = 0; t < d.tiles_a; ++t) tile_a_inst.push_back(i);
-        d.tile_b0 = h->tiles_b;
-        d.tiles_b = 3 * (d.n2 >> p.log2rows);
-        h->tiles_b += d.tiles_b;
-        for (int t = 0; t < d.tiles_b; ++t) tile_b_inst.push_back(i);
-        max_a = std::max(max_a, static_cast<size_t>(3) << (p.log2n2 + p.log2cols));
-        max_b = std::max(max_b, static_cast<size_t>(1) << (p.log2n1 + p.log2rows));
-        // shapes the kernels rely on: a tile fits the per-thread register
-        // budget of an FFT stage, and the butterfly twiddle table covers the
-        // transform lengths
-        const long long maxpts = static_cast<long long>(kThreads) *
-                                 (opt.precision == OPO_F64 ? max_pts<double>() : max_pts<float>());
-        if ((3LL << (p.log2n2 + p.log2cols)) > maxpts || (1LL << (p.log2n1 + p.log2rows)) > maxpts ||
-            d.n1 > kTwL || d.n2 > kTwL || p.log2cols > p.log2n1 || p.log2rows > p.log2n2 ||
-            static_cast<long long>(d.n1) * d.n2 != d.nt)
+        d.tiles_a = (d.n1 + d.cols - 1) / d.cols;
+        d.tiles_b = 3 * ((d.n2 + d.rows - 1) / d.rows);
+        // LDS of a tile: three fields of `cols` columns, or `rows` rows
+        max_a = std::max(max_a, static_cast<size_t>(3) * d.cols * d.n2);
+        max_b = std::max(max_b, static_cast<size_t>(d.rows) * d.n1);
+        // shapes the kernels are instantiated for
+        const int max_ln1 = opt.precision == OPO_F64 ? kMaxLog2N1<double> : kMaxLog2N1<float>;
+        if (p.log2n2 > kMaxLog2N2 || p.log2n1 > max_ln1 || d.n1 > kTwL || d.n2 > kTwL ||
+            static_cast<long long>(d.n1) * d.n2 != d.nt || d.cols < 1 || d.rows < 1)
             return bail(fail(OPO_EINVAL, "internal: tile plan out of bounds for nt " + std::to_string(d.nt)));
 
         // four-step twiddles e^{-2 pi i m/nt}: low table m < 2^b, high table (m >> b) << b
@@ -502,6 +552,58 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
 
     }
 
+    // ---- linear-propagator tables: instances with the same grid, crystal
+    // length and dispersion share one table
+    long long disp_elems = 0;
+    for (int i = 0; i < n; ++i) {
+        InstDesc &d = h->inst[i];
+        int same = -1;
+        for (int o : h->disp_owner) {
+            const InstDesc &e = h->inst[o];
+            if (e.nt == d.nt && e.length_mm == d.length_mm &&
+                std::memcmp(e.disp, d.disp, sizeof(d.disp)) == 0 &&
+                std::memcmp(e.alpha_half, d.alpha_half, sizeof(d.alpha_half)) == 0) {
+                same = o;
+                break;
+            }
+        }
+        if (same >= 0) {
+            d.disp_off = h->inst[same].disp_off;
+        } else {
+            d.disp_off = disp_elems;
+            disp_elems += 3LL * d.nt;
+            h->disp_owner.push_back(i);
+        }
+    }
+
+    // ---- tiles grouped by size range, one launch per group
+    constexpr int ncr = sizeof(kColRanges) / sizeof(kColRanges[0]);
+    constexpr int nrr = sizeof(kRowRanges) / sizeof(kRowRanges[0]);
+    for (int g = 0; g < ncr; ++g) {
+        const int first = h->tiles_a;
+        for (int i = 0; i < n; ++i) {
+            InstDesc &d = h->inst[i];
+            if (range_of(kColRanges, d.log2n2) != g) continue;
+            d.tile_a0 = h->tiles_a;
+            h->tiles_a += d.tiles_a;
+            tile_a_inst.insert(tile_a_inst.end(), d.tiles_a, i);
+        }
+        if (h->tiles_a > first) h->groups_a.push_back({g, first, h->tiles_a - first});
+    }
+    for (int g = 0; g < nrr; ++g) {
+        const int first = h->tiles_b;
+        for (int i = 0; i < n; ++i) {
+            InstDesc &d = h->inst[i];
+            if (range_of(kRowRanges, d.log2n1) != g) continue;
+            d.tile_b0 = h->tiles_b;
+            h->tiles_b += d.tiles_b;
+            tile_b_inst.insert(tile_b_inst.end(), d.tiles_b, i);
+        }
+        if (h->tiles_b > first) h->groups_b.push_back({g, first, h->tiles_b - first});
+    }
+    if (static_cast<int>(tile_a_inst.size()) != h->tiles_a || static_cast<int>(tile_b_inst.size()) != h->tiles_b)
+        return bail(fail(OPO_EINVAL, "internal: a transform length has no kernel"));
+
     // ---- device memory
     if (opt.state) {
         if (opt.state_bytes < need)
@@ -519,8 +621,9 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     if (hipMalloc(reinterpret_cast<void **>(&h->d_inst), n * sizeof(InstDesc)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_tile_a), h->tiles_a * sizeof(int)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_tile_b), h->tiles_b * sizeof(int)) != hipSuccess ||
-        hipMalloc(&h->d_tw, static_cast<size_t>(kTwL) * es) != hipSuccess ||
-        hipMalloc(&h->d_tw4, t4re.size() * es) != hipSuccess ||
+        hipMalloc(&h->d_tw, static_cast<size_t>(kTwL) * 16) != hipSuccess ||
+        hipMalloc(&h->d_tw4, t4re.size() * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&h->d_disp, static_cast<size_t>(disp_elems) * 16) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_partial), h->tiles_a * 3 * sizeof(double)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_hist),
                   static_cast<size_t>(kHistChunk) * n * 3 * sizeof(double)) != hipSuccess ||
@@ -542,13 +645,9 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         hipMemcpyAsync(h->d_tile_b, tile_b_inst.data(), tile_b_inst.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
         return bail(fail(OPO_EDEVICE, "upload of the instance tables failed"));
-    if (opt.precision == OPO_F64) {
-        upload_cplx<double>(h->d_tw, twre, twim, st);
-        upload_cplx<double>(h->d_tw4, t4re, t4im, st);
-    } else {
-        upload_cplx<float>(h->d_tw, twre, twim, st);
-        upload_cplx<float>(h->d_tw4, t4re, t4im, st);
-    }
+    if (opt.precision == OPO_F64) upload_phasors<double>(h->d_tw, twre, twim, st);
+    else upload_phasors<float>(h->d_tw, twre, twim, st);
+    upload_double2(h->d_tw4, t4re, t4im, st);
     std::vector<double> zeros;
     for (int i = 0; i < n; ++i) {
         const InstDesc &d = h->inst[i];
@@ -586,8 +685,26 @@ static int check(opo_t *h)
     return OPO_OK;
 }
 
+// Fill the linear-propagator tables for a step dz (mode > 0) or for each
+// instance's own L/nz (mode 0), unless they already hold that step.
+template <typename R> static int ensure_tables(opo_t *h, double mode)
+{
+    if (h->disp_mode == mode) return OPO_OK;
+    for (int o : h->disp_owner) {
+        const InstDesc &d = h->inst[o];
+        const double dz = mode > 0.0 ? mode : d.length_mm / h->nz;
+        const int blocks = static_cast<int>(std::min<long long>((3LL * d.nt + kThreads - 1) / kThreads, 4096));
+        disp_table<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, o, static_cast<Phasor<R> *>(h->d_disp), dz);
+    }
+    HIP_TRY(hipGetLastError());
+    h->disp_mode = mode;
+    return OPO_OK;
+}
+
 template <typename R> static int propagate_impl(opo_t *h, int nz, double dz)
 {
+    int trc = ensure_tables<R>(h, dz);
+    if (trc) return trc;
     StepArgs<R> a = base_args<R>(h, h->state);
     a.dz_arg = dz;
     a.zbase = h->z;
@@ -601,6 +718,8 @@ template <typename R> static int propagate_impl(opo_t *h, int nz, double dz)
 
 template <typename R> static int roundtrip_impl(opo_t *h, int n_rt)
 {
+    int trc = ensure_tables<R>(h, 0.0);
+    if (trc) return trc;
     if (h->use_graph && !h->graph) {
         hipGraph_t g;
         HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));

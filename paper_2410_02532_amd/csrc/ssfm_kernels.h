@@ -3,22 +3,29 @@
 // (Eq. 6, Sec. 2.3, Sec. 4.1), for a batch of OPO instances of uneven size.
 //
 // Each field of nt = n1*n2 samples is transformed with a four-step FFT: the
-// column pass does n2-point transforms down the columns j1 (stride n1) and
-// multiplies by W_nt^{j1 k2}; the row pass does n1-point transforms along the
-// contiguous rows. A z-step therefore touches HBM twice:
+// column pass does n2-point transforms down the columns j1 (stride n1), the
+// row pass n1-point transforms along the contiguous rows, and the twiddle
+// W_nt^{j1 k2} is applied on both sides of the row pass by the column pass.
+// A z-step therefore touches HBM twice:
 //
-//   column pass  [inverse column FFT] -> [RK4 half-step of the previous step]
-//                -> [round-trip boundary] -> [RK4 half-step of this step]
-//                -> [forward column FFT + twiddle]
-//   row pass     forward row FFT -> linear propagator -> inverse row FFT
-//                -> conjugate twiddle
+//   column pass  [x conj twiddle, inverse column FFT] -> [RK4 half-step of
+//                the previous step] -> [round-trip boundary] -> [RK4
+//                half-step of this step] -> [forward column FFT, x twiddle]
+//   row pass     forward row FFT -> linear propagator / nt -> inverse row FFT
 //
 // The RK4 half-steps (Eqs. 2-4 without the linear operator) are pointwise in
 // time and need the three fields of a sample together, so a column tile holds
-// `cols` columns of all three fields; the linear propagator (Eq. 5) is
-// pointwise in frequency and per field, so a row tile holds `rows` rows of one
-// field. Phase arguments (dispersion, dk z, GDD, EOM) are formed and reduced
-// modulo one revolution in FP64 and only then turned into FP32 phasors.
+// COLS adjacent columns of all three fields (COLS*8 B = 128 B per row, one
+// cache line); the linear propagator (Eq. 5) is pointwise in frequency and
+// per field, so a row tile holds whole rows of one field. Both kernels keep
+// every sample in registers from load to store (fft_tile.h) and are
+// specialized at compile time for the transform length; the host groups the
+// tiles of a batch by that length and launches each group.
+//
+// Phase arguments (dispersion, dk z, GDD, EOM) are formed and reduced modulo
+// one revolution in FP64 and turned into phasors in FP64; in the FP32 path
+// every unit-modulus factor (twiddles, propagator, mirror, GDD, EOM) is then
+// applied as a compensated hi + lo pair (fft_tile.h, Phasor).
 #pragma once
 #include "fft_tile.h"
 
@@ -28,13 +35,14 @@ namespace opo {
 struct InstDesc {
     long long off;        // element offset of the pump field; signal +nt, idler +2nt
     long long pump_off;   // element offset of the input-pump samples, -1 = constant pump
+    long long disp_off;   // offset of the instance's linear-propagator table (3 nt entries)
     int nt, log2nt;
     int n1, log2n1;       // row length (contiguous)
     int n2, log2n2;       // column length (stride n1)
-    int log2cols;         // columns per column tile
-    int log2rows;         // rows per row tile
+    int cols;             // columns per column tile
+    int rows;             // rows per row tile
     int tile_a0, tiles_a; // first column tile of the instance, and count
-    int tile_b0, tiles_b; // first row tile, and count (3 fields x n2/rows)
+    int tile_b0, tiles_b; // first row tile, and count (3 fields x row blocks)
     int tw4_off;          // four-step twiddle tables: 2^tw4_bits low entries, then high
     int tw4_bits;
     int res_mask, gdd_mask, eom_mask, pad0;
@@ -72,9 +80,12 @@ template <typename R> struct StepArgs {
     const int *tile_inst;     // tile -> instance
     cplx<R> *state;
     const cplx<R> *pump;
-    const cplx<R> *tw;        // butterfly twiddles e^{-2 pi i q/kTwL}
-    const cplx<R> *tw4;       // four-step twiddle tables
+    const Phasor<R> *tw;      // butterfly twiddles e^{-2 pi i q/kTwL}
+    const double2 *tw4;       // four-step twiddle tables (FP64)
+    const Phasor<R> *disp;    // linear-propagator tables H_x(k)/nt in row-pass order
     double *partial;          // [column tiles][3] energy partial sums
+    int tile0;                // first tile of this launch (tiles are grouped by shape)
+    int tile_count;           // tiles of this launch
     int flags;
     int step;                 // z-step j whose first half-step this launch runs
     int nz;                   // steps per pass (dz = L/nz when dz_arg <= 0)
@@ -82,103 +93,111 @@ template <typename R> struct StepArgs {
     double zbase;             // z of step 0
 };
 
-// e^{2 pi i rho}, rho reduced modulo 1 in FP64 before the cast.
-template <typename R> __device__ __forceinline__ cplx<R> phasor_rev(double rho);
-template <> __device__ __forceinline__ float2 phasor_rev<float>(double rho)
+// ---------------------------------------------------------------- shapes --
+// Column tile for columns of length 2^ln2: PF samples per thread and field,
+// COLS columns so that COLS * sizeof(complex) = 128 B (one cache line).
+template <typename R> __host__ __device__ constexpr int col_pf(int ln2)
 {
-    const double r = rho - rint(rho);
-    float sn, cs;
-    sincospif(static_cast<float>(2.0 * r), &sn, &cs);
-    return make_float2(cs, sn);
+    const int n = 1 << ln2;
+    const int cmin = 128 / (2 * static_cast<int>(sizeof(R)));
+    const int pfmax = sizeof(R) == 4 ? 16 : 8;
+    if (n == 1) return 1;
+    int pf = cmin * n / kThreads;
+    pf = pf < 2 ? 2 : pf;
+    return pf > pfmax ? pfmax : pf;
 }
-template <> __device__ __forceinline__ double2 phasor_rev<double>(double rho)
+template <typename R> __host__ __device__ constexpr int col_cols(int ln2)
 {
-    const double r = rho - rint(rho);
+    return kThreads * col_pf<R>(ln2) >> ln2;
+}
+// Row tile for rows of length 2^ln1: PF samples per thread, at least 16
+// threads (128 B) along a row, ROWS rows per tile.
+template <typename R> __host__ __device__ constexpr int row_pf(int ln1)
+{
+    const int n = 1 << ln1;
+    if (n == 1) return 1;
+    int pf = n / 16;
+    pf = pf < 2 ? 2 : pf;
+    pf = pf > 8 ? 8 : pf;                        // radix-8 stages need no more
+    return n / pf > kThreads ? n / kThreads : pf;  // at most one row per workgroup
+}
+template <typename R> __host__ __device__ constexpr int row_rows(int ln1)
+{
+    return kThreads * row_pf<R>(ln1) >> ln1;
+}
+template <typename R> constexpr int kMaxLog2N1 = sizeof(R) == 4 ? 12 : 11;   // 256 threads per row
+constexpr int kMaxLog2N2 = 8;
+
+// e^{2 pi i rho} in FP64, rho reduced modulo one revolution first.
+__device__ __forceinline__ double2 unit_rev(double rho)
+{
     double sn, cs;
-    sincospi(2.0 * r, &sn, &cs);
+    sincospi(2.0 * (rho - rint(rho)), &sn, &cs);
     return make_double2(cs, sn);
 }
 
-// e^{i theta} for a small real angle in the working precision.
-template <typename R> __device__ __forceinline__ cplx<R> phasor_small(R th);
-template <> __device__ __forceinline__ float2 phasor_small<float>(float th)
-{
-    float sn, cs;
-    sincosf(th, &sn, &cs);
-    return make_float2(cs, sn);
-}
-template <> __device__ __forceinline__ double2 phasor_small<double>(double th)
-{
-    double sn, cs;
-    sincos(th, &sn, &cs);
-    return make_double2(cs, sn);
-}
-
-template <typename R> __device__ __forceinline__ R sin_rev(double rho);
-template <> __device__ __forceinline__ float sin_rev<float>(double rho)
-{
-    return sinpif(static_cast<float>(2.0 * (rho - rint(rho))));
-}
-template <> __device__ __forceinline__ double sin_rev<double>(double rho)
-{
-    return sinpi(2.0 * (rho - rint(rho)));
-}
-
-// Four-step twiddle W_nt^m = e^{-2 pi i m/nt} from a low and a high table.
+// Four-step twiddle W_nt^m = e^{-2 pi i m/nt}: the product of a low and a
+// high FP64 table entry, formed in FP64.
 template <typename R>
-__device__ __forceinline__ cplx<R> twiddle4(const cplx<R> *__restrict__ t, int bits, unsigned m)
+__device__ __forceinline__ Phasor<R> twiddle4(const double2 *__restrict__ t, int bits, unsigned m)
 {
-    const cplx<R> lo = t[m & ((1u << bits) - 1u)];
-    const cplx<R> hi = t[(1u << bits) + (m >> bits)];
-    return cmul(hi, lo);
+    const double2 lo = t[m & ((1u << bits) - 1u)];
+    const double2 hi = t[(1u << bits) + (m >> bits)];
+    const double2 w = cmul(hi, lo);
+    return make_phasor<R>(w.x, w.y);
 }
 
-// Coupling coefficients of one RK4 stage position z, pre-scaled by h/2:
-// (i kappa_p e^{-i dk z}, i kappa_s e^{+i dk z}, i kappa_i e^{+i dk z}) * h/2.
+// Coupling coefficients of the RK4 stages of the two half-steps a column tile
+// runs, pre-scaled by h/2 (h = dz/2): (i kappa_p e^{-i dk z}, i kappa_s
+// e^{+i dk z}, i kappa_i e^{+i dk z}) * h/2 at z0, z0 + h/2, z0 + h.
 template <typename R> struct Coupling {
-    cplx<R> c[3];
+    cplx<R> c[2][3][3];   // [previous / this half-step][stage position][field]
 };
 
+// Computed by six threads in FP64 and shared through LDS.
 template <typename R>
-__device__ __forceinline__ Coupling<R> coupling_at(const InstDesc &d, double z, double half_h)
+__device__ __forceinline__ void coupling_tile(const InstDesc &d, double z_prev, double z_this,
+                                              double dz, Coupling<R> *out)
 {
     using V = cplx<R>;
-    const double r = d.dk_rev * z;
-    const double rr = r - rint(r);
-    double sn, cs;
-    sincospi(2.0 * rr, &sn, &cs);
-    Coupling<R> k;
-    // i kappa e^{-i th} = kappa (sin th + i cos th); i kappa e^{+i th} = kappa (-sin th + i cos th)
-    const double kp = d.kappa[0] * half_h, ks = d.kappa[1] * half_h, ki = d.kappa[2] * half_h;
-    k.c[0] = mk<V>(static_cast<R>(kp * sn), static_cast<R>(kp * cs));
-    k.c[1] = mk<V>(static_cast<R>(-ks * sn), static_cast<R>(ks * cs));
-    k.c[2] = mk<V>(static_cast<R>(-ki * sn), static_cast<R>(ki * cs));
-    return k;
+    const int q = threadIdx.x;
+    if (q < 6) {
+        const int which = q / 3, st = q - 3 * which;
+        const double z = (which ? z_this : z_prev) + 0.25 * dz * st;
+        const double r = d.dk_rev * z;
+        double sn, cs;
+        sincospi(2.0 * (r - rint(r)), &sn, &cs);
+        const double hh = 0.25 * dz;
+        const double kp = d.kappa[0] * hh, ks = d.kappa[1] * hh, ki = d.kappa[2] * hh;
+        // i kappa e^{-i th} = kappa (sin th + i cos th); i kappa e^{+i th} = kappa (-sin th + i cos th)
+        out->c[which][st][0] = mk<V>(static_cast<R>(kp * sn), static_cast<R>(kp * cs));
+        out->c[which][st][1] = mk<V>(static_cast<R>(-ks * sn), static_cast<R>(ks * cs));
+        out->c[which][st][2] = mk<V>(static_cast<R>(-ki * sn), static_cast<R>(ki * cs));
+    }
 }
 
 // Right-hand side of Eqs. 2-4 (nonlinear part) times h/2.
-template <typename V, typename K>
-__device__ __forceinline__ void cwe_rhs(const K &k, V ap, V as, V ai, V &fp, V &fs, V &fi)
+template <typename V>
+__device__ __forceinline__ void cwe_rhs(const V (&k)[3], V ap, V as, V ai, V &fp, V &fs, V &fi)
 {
-    fp = cmul(k.c[0], cmul(as, ai));
-    fs = cmul(k.c[1], cmulc(ap, ai));
-    fi = cmul(k.c[2], cmulc(ap, as));
+    fp = cmul(k[0], cmul(as, ai));
+    fs = cmul(k[1], cmulc(ap, ai));
+    fi = cmul(k[2], cmulc(ap, as));
 }
 
 // Classical coupled RK4 over one step h with stage coefficients at z0, z0+h/2,
 // z0+h (each pre-scaled by h/2, so y + h/2 k_n becomes y + k'_n).
 template <typename R>
-__device__ __forceinline__ void rk4_point(const Coupling<R> &c0, const Coupling<R> &c1,
-                                          const Coupling<R> &c2, cplx<R> &ap, cplx<R> &as,
+__device__ __forceinline__ void rk4_point(const cplx<R> (&c)[3][3], cplx<R> &ap, cplx<R> &as,
                                           cplx<R> &ai)
 {
     using V = cplx<R>;
     V p1, s1, i1, p2, s2, i2, p3, s3, i3, p4, s4, i4;
-    cwe_rhs(c0, ap, as, ai, p1, s1, i1);
-    cwe_rhs(c1, cadd(ap, p1), cadd(as, s1), cadd(ai, i1), p2, s2, i2);
-    cwe_rhs(c1, cadd(ap, p2), cadd(as, s2), cadd(ai, i2), p3, s3, i3);
+    cwe_rhs(c[0], ap, as, ai, p1, s1, i1);
+    cwe_rhs(c[1], cadd(ap, p1), cadd(as, s1), cadd(ai, i1), p2, s2, i2);
+    cwe_rhs(c[1], cadd(ap, p2), cadd(as, s2), cadd(ai, i2), p3, s3, i3);
     const R two = R(2);
-    cwe_rhs(c2, mk<V>(ap.x + two * p3.x, ap.y + two * p3.y), mk<V>(as.x + two * s3.x, as.y + two * s3.y),
+    cwe_rhs(c[2], mk<V>(ap.x + two * p3.x, ap.y + two * p3.y), mk<V>(as.x + two * s3.x, as.y + two * s3.y),
             mk<V>(ai.x + two * i3.x, ai.y + two * i3.y), p4, s4, i4);
     const R third = R(1) / R(3);
     ap = mk<V>(ap.x + third * (p1.x + two * (p2.x + p3.x) + p4.x),
@@ -214,94 +233,100 @@ __device__ __forceinline__ void block_sum3(double v[3], double *scratch /* [3*kT
         }
 }
 
+struct ColumnShared {
+    double red[3 * kThreads / 64];
+};
+
 // ------------------------------------------------------------------------
-// Column pass: time-domain work of a z-step boundary on `cols` columns of the
-// three fields of one instance.
-template <typename R>
-__global__ __launch_bounds__(kThreads) void column_pass(StepArgs<R> a)
+// Column pass of one tile: COLS columns j1 = c0 + c of the three fields.
+// Thread (c, t) holds samples j2 (or k2) = t + m*T, m < PF, of column c.
+template <typename R, int LN2>
+__device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc &d, int tile,
+                                            cplx<R> *s, Coupling<R> *cpl, double *red)
 {
     using V = cplx<R>;
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    V *s = reinterpret_cast<V *>(lds_raw);
-    __shared__ double red[3 * kThreads / 64];
-
-    const int tile = blockIdx.x;
-    const InstDesc &d = a.inst[a.tile_inst[tile]];
+    constexpr int N = 1 << LN2;
+    constexpr int PF = col_pf<R>(LN2);
+    constexpr int COLS = col_cols<R>(LN2);
+    constexpr int T = N / PF;
     const int flags = a.flags;
-    const int nt = d.nt, n1 = d.n1, log2n2 = d.log2n2, n2 = d.n2;
-    const int log2c = d.log2cols, cols = 1 << log2c;
-    const int c0 = (tile - d.tile_a0) << log2c;
-    const int npts = 3 * cols * n2;   // tile points
-    const int nptf = cols * n2;       // points per field
-    V *g = a.state + d.off;
-
-    for (int q = threadIdx.x; q < npts; q += kThreads) {
-        const int c = q & (cols - 1), rest = q >> log2c;
-        const int j2 = rest & (n2 - 1), f = rest >> log2n2;
-        s[lds_index<R>(((f << log2c) + c) * n2 + j2)] =
-            g[static_cast<long long>(f) * nt + c0 + c + static_cast<long long>(n1) * j2];
-    }
-    __syncthreads();
-    if (flags & A_INV) tile_fft<R, +1>(s, 3 * cols, log2n2, a.tw);
+    const int c = threadIdx.x % COLS, t = threadIdx.x / COLS;
+    const int nt = d.nt, n1 = d.n1;
+    const int j1 = (tile - d.tile_a0) * COLS + c;
+    const bool act = j1 < n1;
+    V *g = a.state + d.off + j1;
 
     const double dz = a.dz_arg > 0.0 ? a.dz_arg : d.length_mm / a.nz;
     const double zb = a.dz_arg > 0.0 ? a.zbase : 0.0;
-    const double half_h = 0.25 * dz;  // h = dz/2, coefficients carry h/2
-    Coupling<R> kp0, kp1, kp2, kt0, kt1, kt2;
-    if (flags & A_RK_PREV) {
-        const double z0 = zb + (a.step - 1) * dz + 0.5 * dz;
-        kp0 = coupling_at<R>(d, z0, half_h);
-        kp1 = coupling_at<R>(d, z0 + 0.25 * dz, half_h);
-        kp2 = coupling_at<R>(d, z0 + 0.5 * dz, half_h);
-    }
-    if (flags & A_RK_THIS) {
-        const double z0 = zb + a.step * dz;
-        kt0 = coupling_at<R>(d, z0, half_h);
-        kt1 = coupling_at<R>(d, z0 + 0.25 * dz, half_h);
-        kt2 = coupling_at<R>(d, z0 + 0.5 * dz, half_h);
-    }
-    V mir[3];
-#pragma unroll
-    for (int x = 0; x < 3; ++x)
-        mir[x] = mk<V>(static_cast<R>(d.mirror[x][0]), static_cast<R>(d.mirror[x][1]));
-    const V pcw = mk<V>(static_cast<R>(d.pump_cw[0]), static_cast<R>(d.pump_cw[1]));
-    const R beta = static_cast<R>(d.eom_beta);
-    double en[3] = {0.0, 0.0, 0.0};
+    if (flags & (A_RK_PREV | A_RK_THIS))
+        coupling_tile<R>(d, zb + (a.step - 1) * dz + 0.5 * dz, zb + a.step * dz, dz, cpl);
 
-    for (int q = threadIdx.x; q < nptf; q += kThreads) {
-        const int c = q >> log2n2, j2 = q & (n2 - 1);
-        const int e0 = lds_index<R>(c * n2 + j2);
-        const int e1 = lds_index<R>((cols + c) * n2 + j2);
-        const int e2 = lds_index<R>((2 * cols + c) * n2 + j2);
-        V y[3] = {s[e0], s[e1], s[e2]};
-        const long long j = static_cast<long long>(c0 + c) + static_cast<long long>(n1) * j2;
-        if (flags & A_RK_PREV) rk4_point<R>(kp0, kp1, kp2, y[0], y[1], y[2]);
-        if (flags & A_ENERGY) {
+    V v[3][PF];
+    Phasor<R> w4[PF];
+    const bool tw_needed = (flags & (A_INV | A_FWD)) && N > 1;
+    if (tw_needed) {
+        const double2 *t4 = a.tw4 + d.tw4_off;
 #pragma unroll
-            for (int x = 0; x < 3; ++x)
-                en[x] += static_cast<double>(y[x].x) * y[x].x + static_cast<double>(y[x].y) * y[x].y;
+        for (int m = 0; m < PF; ++m)
+            w4[m] = twiddle4<R>(t4, d.tw4_bits,
+                                (static_cast<unsigned>(j1) * static_cast<unsigned>(t + m * T)) & (nt - 1));
+    }
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int m = 0; m < PF; ++m)
+            v[f][m] = act ? g[static_cast<long long>(f) * nt + static_cast<long long>(n1) * (t + m * T)]
+                          : mk<V>(R(0), R(0));
+
+    const int base[3] = {c, COLS * N + c, 2 * COLS * N + c};
+    if (flags & A_INV) {
+        if constexpr (N > 1) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int m = 0; m < PF; ++m)
+                    v[f][m] = pmul<true>(v[f][m], w4[m]);
+        }
+        reg_fft<R, N, PF, 3, +1, COLS>(v, s, base, t, a.tw);
+    }
+    if (flags & (A_RK_PREV | A_RK_THIS)) __syncthreads();   // couplings visible
+
+    const V pcw = mk<V>(static_cast<R>(d.pump_cw[0]), static_cast<R>(d.pump_cw[1]));
+    double en[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int m = 0; m < PF; ++m) {
+        const long long j = static_cast<long long>(j1) + static_cast<long long>(n1) * (t + m * T);
+        V y0 = v[0][m], y1 = v[1][m], y2 = v[2][m];
+        if (flags & A_RK_PREV) rk4_point<R>(cpl->c[0], y0, y1, y2);
+        if ((flags & A_ENERGY) && act) {
+            en[0] += static_cast<double>(y0.x) * y0.x + static_cast<double>(y0.y) * y0.y;
+            en[1] += static_cast<double>(y1.x) * y1.x + static_cast<double>(y1.y) * y1.y;
+            en[2] += static_cast<double>(y2.x) * y2.x + static_cast<double>(y2.y) * y2.y;
         }
         if (flags & A_MIRROR) {
-#pragma unroll
-            for (int x = 0; x < 3; ++x)
-                if (d.res_mask & (1 << x)) y[x] = cmul(y[x], mir[x]);
+            if (d.res_mask & 1) y0 = pmul(y0, make_phasor<R>(d.mirror[0][0], d.mirror[0][1]));
+            if (d.res_mask & 2) y1 = pmul(y1, make_phasor<R>(d.mirror[1][0], d.mirror[1][1]));
+            if (d.res_mask & 4) y2 = pmul(y2, make_phasor<R>(d.mirror[2][0], d.mirror[2][1]));
         }
         if ((flags & A_EOM) && d.eom_mask) {
-            const R th = beta * sin_rev<R>(d.eom_rev0 + d.eom_rev_step * static_cast<double>(j));
-            const V e = phasor_small<R>(th);
-#pragma unroll
-            for (int x = 0; x < 3; ++x)
-                if (d.eom_mask & (1 << x)) y[x] = cmul(y[x], e);
+            // beta sin(2 pi f t_j), with f t_j reduced modulo one revolution in FP64
+            const double th = d.eom_beta * unit_rev(d.eom_rev0 + d.eom_rev_step * static_cast<double>(j)).y;
+            double sn, cs;
+            sincos(th, &sn, &cs);
+            const Phasor<R> e = make_phasor<R>(cs, sn);
+            if (d.eom_mask & 1) y0 = pmul(y0, e);
+            if (d.eom_mask & 2) y1 = pmul(y1, e);
+            if (d.eom_mask & 4) y2 = pmul(y2, e);
         }
         if (flags & A_REFRESH) {
-            if (!(d.res_mask & 1)) y[0] = d.pump_off >= 0 ? a.pump[d.pump_off + j] : pcw;
-            if (!(d.res_mask & 2)) y[1] = mk<V>(R(0), R(0));
-            if (!(d.res_mask & 4)) y[2] = mk<V>(R(0), R(0));
+            if (!(d.res_mask & 1)) y0 = (d.pump_off >= 0 && act) ? a.pump[d.pump_off + j] : pcw;
+            if (!(d.res_mask & 2)) y1 = mk<V>(R(0), R(0));
+            if (!(d.res_mask & 4)) y2 = mk<V>(R(0), R(0));
         }
-        if (flags & A_RK_THIS) rk4_point<R>(kt0, kt1, kt2, y[0], y[1], y[2]);
-        s[e0] = y[0];
-        s[e1] = y[1];
-        s[e2] = y[2];
+        if (flags & A_RK_THIS) rk4_point<R>(cpl->c[1], y0, y1, y2);
+        v[0][m] = y0;
+        v[1][m] = y1;
+        v[2][m] = y2;
     }
     if (flags & A_ENERGY) {
         block_sum3(en, red);
@@ -309,97 +334,149 @@ __global__ __launch_bounds__(kThreads) void column_pass(StepArgs<R> a)
             for (int x = 0; x < 3; ++x)
                 a.partial[tile * 3 + x] = en[x];
     }
-    __syncthreads();
 
     if (flags & A_FWD) {
-        tile_fft<R, -1>(s, 3 * cols, log2n2, a.tw);
-        const V *t4 = a.tw4 + d.tw4_off;
-        for (int q = threadIdx.x; q < npts; q += kThreads) {
-            const int c = q & (cols - 1), rest = q >> log2c;
-            const int k2 = rest & (n2 - 1), f = rest >> log2n2;
-            const V v = s[lds_index<R>(((f << log2c) + c) * n2 + k2)];
-            const unsigned m = (static_cast<unsigned>(c0 + c) * static_cast<unsigned>(k2)) & (nt - 1);
-            g[static_cast<long long>(f) * nt + c0 + c + static_cast<long long>(n1) * k2] =
-                cmul(v, twiddle4<R>(t4, d.tw4_bits, m));
+        reg_fft<R, N, PF, 3, -1, COLS>(v, s, base, t, a.tw);
+        if constexpr (N > 1) {
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+#pragma unroll
+                for (int m = 0; m < PF; ++m)
+                    v[f][m] = pmul(v[f][m], w4[m]);
         }
-    } else {
-        for (int q = threadIdx.x; q < npts; q += kThreads) {
-            const int c = q & (cols - 1), rest = q >> log2c;
-            const int j2 = rest & (n2 - 1), f = rest >> log2n2;
-            g[static_cast<long long>(f) * nt + c0 + c + static_cast<long long>(n1) * j2] =
-                s[lds_index<R>(((f << log2c) + c) * n2 + j2)];
-        }
+    }
+    if (act) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int m = 0; m < PF; ++m)
+                g[static_cast<long long>(f) * nt + static_cast<long long>(n1) * (t + m * T)] = v[f][m];
     }
 }
 
+template <typename R, int L, int HI>
+__device__ __forceinline__ void column_dispatch(const StepArgs<R> &a, const InstDesc &d, int tile, cplx<R> *s,
+                                                Coupling<R> *cpl, double *red)
+{
+    if (d.log2n2 == L) column_tile<R, L>(a, d, tile, s, cpl, red);
+    else if constexpr (L < HI) column_dispatch<R, L + 1, HI>(a, d, tile, s, cpl, red);
+}
+
+// Column pass over the tiles of instances whose log2 n2 lies in [LO, HI].
+template <typename R, int LO, int HI>
+__global__ __launch_bounds__(kThreads) void column_pass(StepArgs<R> a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ Coupling<R> cpl;
+    __shared__ double red[3 * kThreads / 64];
+    const int tile = a.tile0 + blockIdx.x;
+    column_dispatch<R, LO, HI>(a, a.inst[a.tile_inst[tile]], tile, reinterpret_cast<cplx<R> *>(lds_raw), &cpl,
+                               red);
+}
+
 // ------------------------------------------------------------------------
-// Row pass: frequency-domain work of a z-step on `rows` rows of one field.
-template <typename R>
-__global__ __launch_bounds__(kThreads) void row_pass(StepArgs<R> a)
+// Row pass of one tile: rows k2 = r0 + w of one field. Thread (w, t) holds
+// samples j1 (or k1) = t + m*T, m < PF, of row w.
+template <typename R, int LN1>
+__device__ __forceinline__ void row_tile(const StepArgs<R> &a, const InstDesc &d, int tile, cplx<R> *s)
 {
     using V = cplx<R>;
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    V *s = reinterpret_cast<V *>(lds_raw);
-
-    const int tile = blockIdx.x;
-    const InstDesc &d = a.inst[a.tile_inst[tile]];
+    constexpr int N = 1 << LN1;
+    constexpr int PF = row_pf<R>(LN1);
+    constexpr int ROWS = row_rows<R>(LN1);
+    constexpr int T = N / PF;
     const int flags = a.flags;
-    const int nt = d.nt, n1 = d.n1, log2n1 = d.log2n1, n2 = d.n2;
-    const int log2r = d.log2rows, rows = 1 << log2r;
+    const int w = threadIdx.x / T, t = threadIdx.x % T;
+    const int nt = d.nt, n2 = d.n2;
+    const int blocks = (n2 + ROWS - 1) / ROWS;
     const int local = tile - d.tile_b0;
-    const int per_field = n2 >> log2r;
-    const int f = local / per_field;
-    const int r0 = (local - f * per_field) << log2r;
-    const int npts = rows * n1;
-    V *g = a.state + d.off + static_cast<long long>(f) * nt + static_cast<long long>(n1) * r0;
+    const int f = local / blocks;
+    const int k2 = (local - f * blocks) * ROWS + w;
+    const bool act = k2 < n2;
+    V *g = a.state + d.off + static_cast<long long>(f) * nt + static_cast<long long>(N) * k2 + t;
 
-    for (int q = threadIdx.x; q < npts; q += kThreads)
-        s[lds_index<R>(q)] = g[q];
-    __syncthreads();
-    tile_fft<R, -1>(s, rows, log2n1, a.tw);
+    V v[1][PF];
+#pragma unroll
+    for (int m = 0; m < PF; ++m)
+        v[0][m] = act ? g[m * T] : mk<V>(R(0), R(0));
+    const int base[1] = {w * N};
+    reg_fft<R, N, PF, 1, -1, 1>(v, s, base, t, a.tw);
 
-    if (flags & B_FWD_ONLY) {
-        for (int q = threadIdx.x; q < npts; q += kThreads)
-            g[q] = s[lds_index<R>(q)];
-        return;
-    }
-
-    const double inv_nt = 1.0 / nt;
-    if (flags & B_DISP) {
-        const double dz = a.dz_arg > 0.0 ? a.dz_arg : d.length_mm / a.nz;
-        const R amp = static_cast<R>(exp(-d.alpha_half[f] * dz) * inv_nt);
-        const double c1 = d.disp[f][0] * dz, c2 = d.disp[f][1] * dz, c3 = d.disp[f][2] * dz;
-        for (int q = threadIdx.x; q < npts; q += kThreads) {
-            const int r = q >> log2n1, k1 = q & (n1 - 1);
-            const int k = (r0 + r) + n2 * k1;
-            const double ks = static_cast<double>(k < (nt >> 1) ? k : k - nt);
-            const double rho = ks * (c1 + ks * (c2 + ks * c3));
-            const int e = lds_index<R>(q);
-            s[e] = cscale(cmul(s[e], phasor_rev<R>(rho)), amp);
-        }
-    } else if (flags & B_GDD) {
-        const bool on = (d.gdd_mask >> f) & 1;
-        const R amp = static_cast<R>(inv_nt);
-        for (int q = threadIdx.x; q < npts; q += kThreads) {
-            const int e = lds_index<R>(q);
-            if (on) {
-                const int r = q >> log2n1, k1 = q & (n1 - 1);
-                const int k = (r0 + r) + n2 * k1;
-                const double ks = static_cast<double>(k < (nt >> 1) ? k : k - nt);
-                s[e] = cscale(cmul(s[e], phasor_rev<R>(d.gdd_rev * ks * ks)), amp);
+    if (!(flags & B_FWD_ONLY)) {
+        if (flags & B_DISP) {
+            // H_f(k)/nt from the instance's table, laid out like the rows
+            const Phasor<R> *h = a.disp + d.disp_off + static_cast<long long>(f) * nt +
+                                 static_cast<long long>(N) * k2 + t;
+#pragma unroll
+            for (int m = 0; m < PF; ++m)
+                if (act) v[0][m] = pmul(v[0][m], h[m * T]);
+        } else if (flags & B_GDD) {
+            const double inv_nt = 1.0 / nt;
+            if ((d.gdd_mask >> f) & 1) {
+#pragma unroll
+                for (int m = 0; m < PF; ++m) {
+                    const int k = k2 + n2 * (t + m * T);
+                    const double ks = static_cast<double>(k < (nt >> 1) ? k : k - nt);
+                    const double2 e = unit_rev(d.gdd_rev * ks * ks);
+                    v[0][m] = pmul(v[0][m], make_phasor<R>(e.x * inv_nt, e.y * inv_nt));
+                }
             } else {
-                s[e] = cscale(s[e], amp);
+#pragma unroll
+                for (int m = 0; m < PF; ++m)
+                    v[0][m] = cscale(v[0][m], static_cast<R>(inv_nt));
             }
         }
+        reg_fft<R, N, PF, 1, +1, 1>(v, s, base, t, a.tw);
     }
-    __syncthreads();
-    tile_fft<R, +1>(s, rows, log2n1, a.tw);
+    if (act)
+#pragma unroll
+        for (int m = 0; m < PF; ++m)
+            g[m * T] = v[0][m];
+}
 
-    const V *t4 = a.tw4 + d.tw4_off;
-    for (int q = threadIdx.x; q < npts; q += kThreads) {
-        const int r = q >> log2n1, j1 = q & (n1 - 1);
-        const unsigned m = (static_cast<unsigned>(j1) * static_cast<unsigned>(r0 + r)) & (nt - 1);
-        g[q] = cmulc(s[lds_index<R>(q)], twiddle4<R>(t4, d.tw4_bits, m));
+template <typename R, int L, int HI>
+__device__ __forceinline__ void row_dispatch(const StepArgs<R> &a, const InstDesc &d, int tile, cplx<R> *s)
+{
+    if (d.log2n1 == L) row_tile<R, L>(a, d, tile, s);
+    else if constexpr (L < HI) row_dispatch<R, L + 1, HI>(a, d, tile, s);
+}
+
+// Row pass over the tiles of instances whose log2 n1 lies in [LO, HI].
+template <typename R, int LO, int HI>
+__global__ __launch_bounds__(kThreads) void row_pass(StepArgs<R> a)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    const int tile = a.tile0 + blockIdx.x;
+    row_dispatch<R, LO, HI>(a, a.inst[a.tile_inst[tile]], tile, reinterpret_cast<cplx<R> *>(lds_raw));
+}
+
+// Size ranges served by one launch: shapes of similar register use share a
+// kernel (the workgroups of different sizes then overlap on the GPU).
+constexpr int kColRanges[][2] = {{0, 6}, {7, 7}, {8, 8}};
+constexpr int kRowRanges[][2] = {{0, 5}, {6, 11}, {12, 12}};
+
+// ------------------------------------------------------------------------
+// Linear propagator of one z-step (Eq. 5) for the three fields of an instance,
+// H_x(k)/nt = exp{[-alpha_x/2 + i(-db1 w + b2 w^2/2 - b3 w^3/6)] dz}/nt,
+// formed in FP64 (phase reduced modulo one revolution) and stored in the
+// row-pass order: position k2*n1 + k1 holds bin k = k2 + n2*k1.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void disp_table(const InstDesc *inst, int owner, Phasor<R> *out,
+                                                       double dz)
+{
+    const InstDesc &d = inst[owner];
+    const long long n = 3LL * d.nt;
+    for (long long q = blockIdx.x * static_cast<long long>(kThreads) + threadIdx.x; q < n;
+         q += static_cast<long long>(gridDim.x) * kThreads) {
+        const int f = static_cast<int>(q / d.nt);
+        const int p = static_cast<int>(q - static_cast<long long>(f) * d.nt);
+        const int k2 = p >> d.log2n1, k1 = p & (d.n1 - 1);
+        const int k = k2 + d.n2 * k1;
+        const double ks = static_cast<double>(k < (d.nt >> 1) ? k : k - d.nt);
+        const double rho = dz * ks * (d.disp[f][0] + ks * (d.disp[f][1] + ks * d.disp[f][2]));
+        const double amp = exp(-d.alpha_half[f] * dz) / d.nt;
+        const double2 e = unit_rev(rho);
+        out[d.disp_off + q] = make_phasor<R>(amp * e.x, amp * e.y);
     }
 }
 

@@ -1,0 +1,151 @@
+"""Long runs and full-size workloads on the GPU against the FP64 oracle.
+
+Expected values of long runs are stored under tests/golden/ (written by
+tests/golden/make_golden.py, which calls only the oracle). Full-size batches
+are checked on sampled instances that the oracle runs one by one.
+
+Bars (complex64 fields, FP64 phase arguments and energies): round-trip energies
+within 1e-3 relative (the target for output power after 1000 round trips),
+fields within 1e-4 relative L2 per pass; complex128 within 1e-9 / 1e-11.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import torch  # noqa: F401  (imported at collection: the first import can take minutes)
+
+import oracle
+from paper_2410_02532_amd import opo as B
+from paper_2410_02532_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, name + ".json")) as f:
+        return json.load(f)
+
+
+def _rel(got, ref):
+    return np.abs(np.asarray(got) - np.asarray(ref)) / np.abs(np.asarray(ref))
+
+
+def _check_energies(hist, g, tol, fields=(0, 1, 2)):
+    rts = g["energy_rt"]
+    ref = np.array(g["energy"])
+    got = hist[rts]
+    for x in fields:
+        err = _rel(got[:, x], ref[:, x])
+        assert np.max(err) <= tol, (x, float(np.max(err)), rts[int(np.argmax(err))])
+
+
+@pytest.mark.parametrize("precision, tol", [("f32", 1e-3), ("f64", 1e-9)])
+def test_sro_2000_round_trips_full_size(precision, tol):
+    """CW SRO at Nt = 2^14, Nz = 100: energies of all three fields over 2000 round trips
+    (including the output signal power after 1000) against the oracle."""
+    g = golden("sro_cw_2000rt")
+    say("SRO 2^14, 2000 RT,", precision)
+    w = W.config("sro_cw", precision=precision)
+    with B.from_workload(w) as h:
+        h.cavity_roundtrip(2000)
+        hist = h.energy_history()
+    assert hist.shape == (2000, 3)
+    _check_energies(hist, g, tol)
+    assert 999 in g["energy_rt"]
+
+
+def test_sro_depleted_steady_state():
+    """A strongly pumped SRO (6x threshold, R = 0.90) that depletes the pump: the long-run
+    energies of the saturated state against the oracle."""
+    g = golden("sro_cw_depleted_4096")
+    nt = g["nt"]
+    cr = W.crystal(nt)
+    ap0 = np.sqrt(6.0) * W.threshold_amplitude(cr, 0.90)
+    ins = dict(crystal=cr, cavity=W.cavity(refl=(0.0, 0.90, 0.0)), fields=W.initial_fields(nt, ap0, 1000),
+               pump_in=np.full(nt, ap0 + 0j))
+    say("depleted SRO 4096, 500 RT")
+    with B.Opo([ins], g["nz"], precision="f32") as h:
+        h.cavity_roundtrip(g["n_rt"])
+        hist = h.energy_history()
+    _check_energies(hist, g, 1e-3)
+    e = np.array(g["energy"])
+    assert e[-1, 0] < 0.3 * e[0, 0]   # the pump is depleted in this regime
+
+
+def test_sync_pumped_1000_round_trips():
+    """Synchronously pumped OPO (2 ps pump, TOD) at Nt = 2^16 over 1000 round trips."""
+    g = golden("sync_pumped_65536")
+    say("sync-pumped 2^16, 1000 RT")
+    w = W.config("sync_pumped", nt=1 << 16)
+    with B.from_workload(w) as h:
+        h.cavity_roundtrip(g["n_rt"])
+        hist = h.energy_history()
+    _check_energies(hist, g, 1e-3)
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_sync_pumped_2_18_one_round_trip(precision):
+    """The largest synchronously pumped grid, Nt = 2^18, one round trip: every field sample."""
+    say("sync-pumped 2^18, 1 RT,", precision)
+    w = W.config("sync_pumped", nt=1 << 18)
+    ref, e_ref = oracle.roundtrips(w["crystal"], w["cavity"], w["fields"], w["pump_in"], w["nz"], 1)
+    with B.from_workload(w, precision=precision) as h:
+        h.cavity_roundtrip(1)
+        got = h.get_fields()
+        e = h.energy_history()
+    # complex128: the third-order dispersion phase reaches ~2.3e3 rad per step at the Nyquist
+    # edge of this grid, whose FP64 argument carries ~2.3e3 * 1.1e-16 = 2.6e-13 rad of rounding
+    # that the two implementations round differently; over 100 steps that allows ~1e-11..1e-10
+    tol = 1e-4 if precision == "f32" else 1e-10
+    for x in range(3):
+        assert np.linalg.norm(got[x] - ref[x]) / np.linalg.norm(ref[x]) <= tol
+        assert abs(e[0, x] - e_ref[0, x]) / e_ref[0, x] <= (1e-4 if precision == "f32" else 1e-10)
+
+
+def test_dro_large_batch_full_size():
+    """The large doubly resonant batch at full size (16 x 2^20, Nz = 200, GDD +-2000 fs^2,
+    EOM 1 rad at 1/T): three round trips; instances 0 (+GDD) and 8 (-GDD) against the oracle's
+    energies and sampled fields."""
+    say("DRO 16 x 2^20, 3 RT")
+    w = W.config("dro_large", n_rt=3)
+    with B.from_workload(w) as h:
+        h.cavity_roundtrip(3)
+        res = {i: (h.energy_history(i), h.get_fields(i)) for i in (0, 8)}
+    for i in (0, 8):
+        g = golden("dro_large_inst%d" % i)
+        hist, a = res[i]
+        _check_energies(hist, g, 1e-3)
+        idx = np.array(g["sample_index"])
+        for x in range(3):
+            ref = np.array(g["final_re"][x]) + 1j * np.array(g["final_im"][x])
+            assert np.max(np.abs(a[x, idx] - ref)) <= 1e-3 * np.max(np.abs(ref)), (i, x)
+
+
+def test_batched_sweep_full_size_sampled():
+    """The 256-instance batched sweep in the benchmark's launch configuration, two round
+    trips; one instance of every size is replayed by the oracle."""
+    say("batched sweep 256, 2 RT")
+    w = W.config("batched_sweep")
+    insts = w["instances"]
+    with B.from_workload(w) as h:
+        h.cavity_roundtrip(2)
+        picks = {}
+        for i, ins in enumerate(insts):
+            picks.setdefault(ins["crystal"]["nt"], i)
+        got = {i: (h.get_fields(i), h.energy_history(i)) for i in picks.values()}
+    assert len(picks) == 5
+    for i, (a, e) in got.items():
+        ins = insts[i]
+        ref, e_ref = oracle.roundtrips(ins["crystal"], ins["cavity"], ins["fields"], ins["pump_in"], w["nz"], 2)
+        for x in range(3):
+            assert np.linalg.norm(a[x] - ref[x]) / np.linalg.norm(ref[x]) <= 2e-4, (i, x)
+            assert np.max(_rel(e[:, x], e_ref[:, x])) <= 1e-3
