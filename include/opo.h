@@ -167,8 +167,10 @@ int opo_get_energy_history(opo_t *h, int32_t inst, double *out, int32_t capacity
 /* Time samples t_j [ps] and angular frequencies w_k [rad/ps] of an instance. */
 int opo_get_grid(opo_t *h, int32_t inst, double *t, double *omega);
 
-/* Kernel classes timed by the profile option. */
-enum { OPO_K_COLUMN = 0, OPO_K_ROW = 1, OPO_K_ENERGY = 2, OPO_K_CLASSES = 3 };
+/* Kernel classes timed by the profile option: column pass, row pass, energy
+ * reduction, and the mixed pass that runs the column tiles of one half of a
+ * batch together with the row tiles of the other half. */
+enum { OPO_K_COLUMN = 0, OPO_K_ROW = 1, OPO_K_ENERGY = 2, OPO_K_MIXED = 3, OPO_K_CLASSES = 4 };
 
 /* Device time [ms] summed over launches, and launch counts, of each kernel
  * class since the handle was created (profile option), OPO_K_CLASSES

@@ -13,7 +13,7 @@
 // one read back of the thread's own positions). In the last stage P = N/RS,
 // so j = i and the outputs land on the thread's own positions: the result
 // comes back in natural order in registers, with no LDS traffic. Twiddles
-// come from one table e^{-2 pi i q/kTwL} built on the host in FP64 (held as
+// come from a stage-major table built on the host in FP64 (held as
 // compensated FP32 pairs in the FP32 path), and are loaded once per stage and
 // reused for every transform the thread owns.
 #pragma once
@@ -22,7 +22,25 @@
 namespace opo {
 
 constexpr int kThreads = 256;   // threads per workgroup of every tile kernel
-constexpr int kTwL = 8192;      // length of the butterfly twiddle table
+constexpr int kTwL = 8192;      // longest transform the twiddle table serves
+
+// Stage-major twiddle table: for a stage of radix RS after sub-transforms of
+// length P, the factors w^{r k} = e^{-2 pi i r k/(P RS)}, r = 1..RS-1, of
+// butterfly class k < P sit at tw_index(RS, P, k) + r - 1. One thread's
+// factors are contiguous and consecutive k are adjacent, so a stage reads a
+// compact, coalesced block instead of strided entries of one long table.
+// Entries of radix rs: P runs over the powers of two with P*rs <= kTwL, and
+// sum_{P = 1, 2, ..., M} P = 2M - 1.
+__host__ __device__ constexpr int tw_block_size(int rs) { return (2 * (kTwL / rs) - 1) * (rs - 1); }
+__host__ __device__ constexpr int tw_block(int rs)
+{
+    return rs == 2 ? 0 : rs == 4 ? tw_block_size(2) : tw_block_size(2) + tw_block_size(4);
+}
+__host__ __device__ constexpr int tw_index(int rs, int p, int k)
+{
+    return tw_block(rs) + (p - 1 + k) * (rs - 1);
+}
+constexpr int kTwEntries = tw_block_size(2) + tw_block_size(4) + tw_block_size(8);
 
 template <typename R> struct cplx_of;
 template <> struct cplx_of<float> { using type = float2; };
@@ -203,9 +221,10 @@ __device__ __forceinline__ void reg_stage(cplx<R> (&v)[NTR][PF], cplx<R> *lds, c
 #pragma unroll
         for (int u = 0; u < NBT; ++u) {
             const int k = (t + u * STRIDE) & (P - 1);
+            const Phasor<R> *q = tw + tw_index(RS, P, k);
 #pragma unroll
             for (int r = 1; r < RS; ++r)
-                w[u][r] = tw[r * k * (kTwL / (P * RS))];
+                w[u][r] = q[r - 1];
         }
     }
 #pragma unroll

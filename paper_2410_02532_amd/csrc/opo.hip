@@ -67,6 +67,7 @@ struct Group {
     int ln;       // index of the size range
     int tile0;    // first tile
     int count;    // tiles
+    int half;     // half of the batch (mixed schedule), 0 otherwise
 };
 
 // Index of the size range (kColRanges / kRowRanges) that contains ln.
@@ -100,6 +101,29 @@ template <typename R> static const void *row_fn(int range)
     }
 }
 
+// Mixed column/row kernels for the (column range, row range) pairs that the
+// four-step split produces.
+template <typename R> static const void *mixed_fn(int cr, int rr)
+{
+    const int key = cr * 3 + rr;
+    switch (key) {
+    case 0: return reinterpret_cast<const void *>(&mixed_pass<R, 0, 0>);
+    case 1: return reinterpret_cast<const void *>(&mixed_pass<R, 0, 1>);
+    case 2:
+        if constexpr (kMaxLog2N1<R> >= kRowRanges[2][0]) return reinterpret_cast<const void *>(&mixed_pass<R, 0, 2>);
+        return nullptr;
+    case 4: return reinterpret_cast<const void *>(&mixed_pass<R, 1, 1>);
+    case 5:
+        if constexpr (kMaxLog2N1<R> >= kRowRanges[2][0]) return reinterpret_cast<const void *>(&mixed_pass<R, 1, 2>);
+        return nullptr;
+    case 7: return reinterpret_cast<const void *>(&mixed_pass<R, 2, 1>);
+    case 8:
+        if constexpr (kMaxLog2N1<R> >= kRowRanges[2][0]) return reinterpret_cast<const void *>(&mixed_pass<R, 2, 2>);
+        return nullptr;
+    default: return nullptr;
+    }
+}
+
 } // namespace opo
 
 using namespace opo;
@@ -119,7 +143,8 @@ struct opo_s {
     std::vector<InstDesc> inst;
     InstDesc *d_inst = nullptr;
     int tiles_a = 0, tiles_b = 0;
-    std::vector<Group> groups_a, groups_b;   // tiles of one transform length
+    std::vector<Group> groups_a, groups_b;   // tiles of one size range (and half)
+    bool mixed = false;              // two halves a launch apart, mixed launches
     int *d_tile_a = nullptr, *d_tile_b = nullptr;
     void *d_tw = nullptr, *d_tw4 = nullptr;
     void *d_disp = nullptr;          // linear-propagator tables, one per distinct crystal/grid
@@ -142,8 +167,8 @@ struct opo_s {
     std::vector<hipEvent_t> events;
     std::vector<int> ev_class;
     size_t ev_used = 0;
-    double k_ms[OPO_K_CLASSES] = {0.0, 0.0, 0.0};
-    long long k_count[OPO_K_CLASSES] = {0, 0, 0};
+    double k_ms[OPO_K_CLASSES] = {};
+    long long k_count[OPO_K_CLASSES] = {};
 };
 
 namespace opo {
@@ -348,13 +373,14 @@ static int prof_collect(opo_t *h, size_t used)
     return OPO_OK;
 }
 
-template <typename R> static void launch_a(opo_t *h, StepArgs<R> a, int flags, int step)
+template <typename R> static void launch_a(opo_t *h, StepArgs<R> a, int flags, int step, int half = -1)
 {
     a.tile_inst = h->d_tile_a;
     a.flags = flags;
     a.step = step;
     prof_begin(h, OPO_K_COLUMN);
     for (const Group &g : h->groups_a) {
+        if (half >= 0 && g.half != half) continue;
         a.tile0 = g.tile0;
         a.tile_count = g.count;
         void *args[] = {&a};
@@ -377,11 +403,44 @@ template <typename R> static void launch_b(opo_t *h, StepArgs<R> a, int flags)
     prof_end(h);
 }
 
+// Column tiles of half `ch` (flags, step) with the row tiles (B_DISP) of the
+// other half, in one launch.
+template <typename R> static void launch_mixed(opo_t *h, StepArgs<R> a, int ch, int cflags, int step)
+{
+    const Group &gc = h->groups_a[ch], &gr = h->groups_b[1 - ch];
+    StepArgs<R> ac = a, ar = a;
+    ac.tile_inst = h->d_tile_a;
+    ac.flags = cflags;
+    ac.step = step;
+    ac.tile0 = gc.tile0;
+    ac.tile_count = gc.count;
+    ar.tile_inst = h->d_tile_b;
+    ar.flags = B_DISP;
+    ar.tile0 = gr.tile0;
+    ar.tile_count = gr.count;
+    void *args[] = {&ac, &ar};
+    prof_begin(h, OPO_K_MIXED);
+    (void)hipLaunchKernel(mixed_fn<R>(gc.ln, gr.ln), dim3(gc.count + gr.count), dim3(kThreads), args,
+                          std::max(h->lds_a, h->lds_b), h->stream);
+    prof_end(h);
+}
+
 // One crystal pass of nz steps. `first` flags are OR-ed into the opening
 // column pass (refresh), `last` into the closing one (energy, mirror, EOM).
 template <typename R>
 static void enqueue_pass(opo_t *h, StepArgs<R> a, int nz, int first, int last)
 {
+    if (h->mixed) {
+        // half 0 runs one launch ahead of half 1
+        const int mid = A_INV | A_RK_PREV | A_RK_THIS | A_FWD;
+        launch_a<R>(h, a, first | A_RK_THIS | A_FWD, 0, 0);
+        for (int j = 0; j < nz; ++j) {
+            launch_mixed<R>(h, a, 1, j == 0 ? (first | A_RK_THIS | A_FWD) : mid, j);      // rows of half 0
+            launch_mixed<R>(h, a, 0, j + 1 < nz ? mid : (A_INV | A_RK_PREV | last), j + 1);  // rows of half 1
+        }
+        launch_a<R>(h, a, A_INV | A_RK_PREV | last, nz, 1);
+        return;
+    }
     launch_a<R>(h, a, first | A_RK_THIS | A_FWD, 0);
     for (int j = 0; j < nz; ++j) {
         launch_b<R>(h, a, B_DISP);
@@ -422,6 +481,11 @@ template <typename R> static int setup_kernels(opo_t *h)
         HIP_TRY(hipFuncSetAttribute(row_fn<R>(g.ln), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     static_cast<int>(h->lds_b)));
     }
+    if (h->mixed)
+        for (int hf = 0; hf < 2; ++hf)
+            HIP_TRY(hipFuncSetAttribute(mixed_fn<R>(h->groups_a[1 - hf].ln, h->groups_b[hf].ln),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        static_cast<int>(std::max(h->lds_a, h->lds_b))));
     return OPO_OK;
 }
 
@@ -576,33 +640,62 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         }
     }
 
-    // ---- tiles grouped by size range, one launch per group
+    // ---- halves of a batch for the mixed schedule: instances are dealt to
+    // two halves of similar size (largest first); the schedule is used when
+    // each half then has one column and one row size range and no GDD pass
+    std::vector<int> half(n, 0);
+    if (n >= 2 && !h->any_gdd) {
+        std::vector<int> order(n);
+        for (int i = 0; i < n; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return h->inst[x].nt > h->inst[y].nt; });
+        long long load[2] = {0, 0};
+        for (int i : order) {
+            const int hf = load[0] <= load[1] ? 0 : 1;
+            half[i] = hf;
+            load[hf] += h->inst[i].nt;
+        }
+    }
+    // ---- tiles grouped by half and size range, one launch per group
     constexpr int ncr = sizeof(kColRanges) / sizeof(kColRanges[0]);
     constexpr int nrr = sizeof(kRowRanges) / sizeof(kRowRanges[0]);
-    for (int g = 0; g < ncr; ++g) {
-        const int first = h->tiles_a;
-        for (int i = 0; i < n; ++i) {
-            InstDesc &d = h->inst[i];
-            if (range_of(kColRanges, d.log2n2) != g) continue;
-            d.tile_a0 = h->tiles_a;
-            h->tiles_a += d.tiles_a;
-            tile_a_inst.insert(tile_a_inst.end(), d.tiles_a, i);
+    for (int hf = 0; hf < 2; ++hf)
+        for (int g = 0; g < ncr; ++g) {
+            const int first = h->tiles_a;
+            for (int i = 0; i < n; ++i) {
+                InstDesc &d = h->inst[i];
+                if (half[i] != hf || range_of(kColRanges, d.log2n2) != g) continue;
+                d.tile_a0 = h->tiles_a;
+                h->tiles_a += d.tiles_a;
+                tile_a_inst.insert(tile_a_inst.end(), d.tiles_a, i);
+            }
+            if (h->tiles_a > first) h->groups_a.push_back({g, first, h->tiles_a - first, hf});
         }
-        if (h->tiles_a > first) h->groups_a.push_back({g, first, h->tiles_a - first});
-    }
-    for (int g = 0; g < nrr; ++g) {
-        const int first = h->tiles_b;
-        for (int i = 0; i < n; ++i) {
-            InstDesc &d = h->inst[i];
-            if (range_of(kRowRanges, d.log2n1) != g) continue;
-            d.tile_b0 = h->tiles_b;
-            h->tiles_b += d.tiles_b;
-            tile_b_inst.insert(tile_b_inst.end(), d.tiles_b, i);
+    for (int hf = 0; hf < 2; ++hf)
+        for (int g = 0; g < nrr; ++g) {
+            const int first = h->tiles_b;
+            for (int i = 0; i < n; ++i) {
+                InstDesc &d = h->inst[i];
+                if (half[i] != hf || range_of(kRowRanges, d.log2n1) != g) continue;
+                d.tile_b0 = h->tiles_b;
+                h->tiles_b += d.tiles_b;
+                tile_b_inst.insert(tile_b_inst.end(), d.tiles_b, i);
+            }
+            if (h->tiles_b > first) h->groups_b.push_back({g, first, h->tiles_b - first, hf});
         }
-        if (h->tiles_b > first) h->groups_b.push_back({g, first, h->tiles_b - first});
-    }
     if (static_cast<int>(tile_a_inst.size()) != h->tiles_a || static_cast<int>(tile_b_inst.size()) != h->tiles_b)
         return bail(fail(OPO_EINVAL, "internal: a transform length has no kernel"));
+    if (n >= 2 && !h->any_gdd && h->groups_a.size() == 2 && h->groups_b.size() == 2 &&
+        h->groups_a[0].half == 0 && h->groups_a[1].half == 1 && h->groups_b[0].half == 0 &&
+        h->groups_b[1].half == 1) {
+        const bool f64 = opt.precision == OPO_F64;
+        h->mixed = true;
+        for (int hf = 0; hf < 2; ++hf) {
+            const void *fn = f64 ? mixed_fn<double>(h->groups_a[1 - hf].ln, h->groups_b[hf].ln)
+                                 : mixed_fn<float>(h->groups_a[1 - hf].ln, h->groups_b[hf].ln);
+            h->mixed = h->mixed && fn != nullptr;
+        }
+    }
 
     // ---- device memory
     if (opt.state) {
@@ -621,7 +714,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     if (hipMalloc(reinterpret_cast<void **>(&h->d_inst), n * sizeof(InstDesc)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_tile_a), h->tiles_a * sizeof(int)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_tile_b), h->tiles_b * sizeof(int)) != hipSuccess ||
-        hipMalloc(&h->d_tw, static_cast<size_t>(kTwL) * 16) != hipSuccess ||
+        hipMalloc(&h->d_tw, static_cast<size_t>(kTwEntries) * 16) != hipSuccess ||
         hipMalloc(&h->d_tw4, t4re.size() * sizeof(double2)) != hipSuccess ||
         hipMalloc(&h->d_disp, static_cast<size_t>(disp_elems) * 16) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_partial), h->tiles_a * 3 * sizeof(double)) != hipSuccess ||
@@ -637,8 +730,16 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     if (h->lds_a > 160 * 1024 || h->lds_b > 160 * 1024)
         return bail(fail(OPO_EINVAL, "internal: tile needs more LDS than a workgroup has"));
 
-    std::vector<double> twre, twim;
-    build_twiddles_rows(twre, twim, kTwL, kTwL, 1.0);
+    // stage-major butterfly twiddles (fft_tile.h, tw_index)
+    std::vector<double> twre(kTwEntries, 1.0), twim(kTwEntries, 0.0);
+    for (int rs : {2, 4, 8})
+        for (int p = 1; p * rs <= kTwL; p *= 2)
+            for (int k = 0; k < p; ++k)
+                for (int r = 1; r < rs; ++r) {
+                    const double a = kTwoPi * static_cast<double>(r * k) / static_cast<double>(p * rs);
+                    twre[tw_index(rs, p, k) + r - 1] = std::cos(a);
+                    twim[tw_index(rs, p, k) + r - 1] = -std::sin(a);
+                }
     hipStream_t st = h->stream;
     if (hipMemcpyAsync(h->d_inst, h->inst.data(), n * sizeof(InstDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(h->d_tile_a, tile_a_inst.data(), tile_a_inst.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||

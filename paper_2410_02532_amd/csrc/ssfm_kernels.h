@@ -176,29 +176,37 @@ __device__ __forceinline__ void coupling_tile(const InstDesc &d, double z_prev, 
     }
 }
 
+// k * t; with IMAG the coefficient is known to be purely imaginary (dk = 0,
+// so e^{+-i dk z} = 1 and k = i kappa h/2) and its zero real part is skipped.
+template <bool IMAG, typename V> __device__ __forceinline__ V kmul(V k, V t)
+{
+    if constexpr (IMAG) return mk<V>(-k.y * t.y, k.y * t.x);
+    else return cmul(k, t);
+}
+
 // Right-hand side of Eqs. 2-4 (nonlinear part) times h/2.
-template <typename V>
+template <bool IMAG, typename V>
 __device__ __forceinline__ void cwe_rhs(const V (&k)[3], V ap, V as, V ai, V &fp, V &fs, V &fi)
 {
-    fp = cmul(k[0], cmul(as, ai));
-    fs = cmul(k[1], cmulc(ap, ai));
-    fi = cmul(k[2], cmulc(ap, as));
+    fp = kmul<IMAG>(k[0], cmul(as, ai));
+    fs = kmul<IMAG>(k[1], cmulc(ap, ai));
+    fi = kmul<IMAG>(k[2], cmulc(ap, as));
 }
 
 // Classical coupled RK4 over one step h with stage coefficients at z0, z0+h/2,
 // z0+h (each pre-scaled by h/2, so y + h/2 k_n becomes y + k'_n).
-template <typename R>
+template <typename R, bool IMAG>
 __device__ __forceinline__ void rk4_point(const cplx<R> (&c)[3][3], cplx<R> &ap, cplx<R> &as,
                                           cplx<R> &ai)
 {
     using V = cplx<R>;
     V p1, s1, i1, p2, s2, i2, p3, s3, i3, p4, s4, i4;
-    cwe_rhs(c[0], ap, as, ai, p1, s1, i1);
-    cwe_rhs(c[1], cadd(ap, p1), cadd(as, s1), cadd(ai, i1), p2, s2, i2);
-    cwe_rhs(c[1], cadd(ap, p2), cadd(as, s2), cadd(ai, i2), p3, s3, i3);
+    cwe_rhs<IMAG>(c[0], ap, as, ai, p1, s1, i1);
+    cwe_rhs<IMAG>(c[1], cadd(ap, p1), cadd(as, s1), cadd(ai, i1), p2, s2, i2);
+    cwe_rhs<IMAG>(c[1], cadd(ap, p2), cadd(as, s2), cadd(ai, i2), p3, s3, i3);
     const R two = R(2);
-    cwe_rhs(c[2], mk<V>(ap.x + two * p3.x, ap.y + two * p3.y), mk<V>(as.x + two * s3.x, as.y + two * s3.y),
-            mk<V>(ai.x + two * i3.x, ai.y + two * i3.y), p4, s4, i4);
+    cwe_rhs<IMAG>(c[2], mk<V>(ap.x + two * p3.x, ap.y + two * p3.y), mk<V>(as.x + two * s3.x, as.y + two * s3.y),
+                  mk<V>(ai.x + two * i3.x, ai.y + two * i3.y), p4, s4, i4);
     const R third = R(1) / R(3);
     ap = mk<V>(ap.x + third * (p1.x + two * (p2.x + p3.x) + p4.x),
                ap.y + third * (p1.y + two * (p2.y + p3.y) + p4.y));
@@ -292,12 +300,16 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     if (flags & (A_RK_PREV | A_RK_THIS)) __syncthreads();   // couplings visible
 
     const V pcw = mk<V>(static_cast<R>(d.pump_cw[0]), static_cast<R>(d.pump_cw[1]));
+    const bool imag = d.dk_rev == 0.0;   // couplings i kappa h/2 without a phase
     double en[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int m = 0; m < PF; ++m) {
         const long long j = static_cast<long long>(j1) + static_cast<long long>(n1) * (t + m * T);
         V y0 = v[0][m], y1 = v[1][m], y2 = v[2][m];
-        if (flags & A_RK_PREV) rk4_point<R>(cpl->c[0], y0, y1, y2);
+        if (flags & A_RK_PREV) {
+            if (imag) rk4_point<R, true>(cpl->c[0], y0, y1, y2);
+            else rk4_point<R, false>(cpl->c[0], y0, y1, y2);
+        }
         if ((flags & A_ENERGY) && act) {
             en[0] += static_cast<double>(y0.x) * y0.x + static_cast<double>(y0.y) * y0.y;
             en[1] += static_cast<double>(y1.x) * y1.x + static_cast<double>(y1.y) * y1.y;
@@ -323,7 +335,10 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
             if (!(d.res_mask & 2)) y1 = mk<V>(R(0), R(0));
             if (!(d.res_mask & 4)) y2 = mk<V>(R(0), R(0));
         }
-        if (flags & A_RK_THIS) rk4_point<R>(cpl->c[1], y0, y1, y2);
+        if (flags & A_RK_THIS) {
+            if (imag) rk4_point<R, true>(cpl->c[1], y0, y1, y2);
+            else rk4_point<R, false>(cpl->c[1], y0, y1, y2);
+        }
         v[0][m] = y0;
         v[1][m] = y1;
         v[2][m] = y2;
@@ -454,6 +469,33 @@ __global__ __launch_bounds__(kThreads) void row_pass(StepArgs<R> a)
 // kernel (the workgroups of different sizes then overlap on the GPU).
 constexpr int kColRanges[][2] = {{0, 6}, {7, 7}, {8, 8}};
 constexpr int kRowRanges[][2] = {{0, 5}, {6, 11}, {12, 12}};
+
+// ------------------------------------------------------------------------
+// Mixed pass: the column tiles of one half of a batch and the row tiles of
+// the other half in one launch. The halves are a launch apart in their z-step
+// sequences, so every launch pairs the VALU-bound column work of one half
+// with the memory-latency-bound row work of the other. Workgroups alternate
+// between the two kinds in proportion to their counts, so that every CU gets
+// both.
+template <typename R, int CR, int RR>
+__global__ __launch_bounds__(kThreads) void mixed_pass(StepArgs<R> ac, StepArgs<R> ar)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ Coupling<R> cpl;
+    __shared__ double red[3 * kThreads / 64];
+    cplx<R> *s = reinterpret_cast<cplx<R> *>(lds_raw);
+    const long long nc = ac.tile_count, total = nc + ar.tile_count;
+    const long long b = blockIdx.x;
+    const long long before = b * nc / total;            // column tiles among blocks < b
+    if ((b + 1) * nc / total > before) {
+        const int tile = ac.tile0 + static_cast<int>(before);
+        column_dispatch<R, kColRanges[CR][0], kColRanges[CR][1]>(ac, ac.inst[ac.tile_inst[tile]], tile, s, &cpl,
+                                                                 red);
+    } else {
+        const int tile = ar.tile0 + static_cast<int>(b - before);
+        row_dispatch<R, kRowRanges[RR][0], kRowRanges[RR][1]>(ar, ar.inst[ar.tile_inst[tile]], tile, s);
+    }
+}
 
 // ------------------------------------------------------------------------
 // Linear propagator of one z-step (Eq. 5) for the three fields of an instance,

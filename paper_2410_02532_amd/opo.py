@@ -20,7 +20,7 @@ STATUS = {0: "OPO_OK", -1: "OPO_EINVAL", -2: "OPO_ENOMEM", -3: "OPO_EDEVICE",
 EXPORTS = ("opo_state_bytes", "opo_init", "opo_init_batch", "ssfm_propagate", "cavity_roundtrip",
            "opo_sync", "opo_get_fields", "opo_set_fields", "opo_get_energy_history",
            "opo_get_grid", "opo_kernel_times", "opo_info", "opo_destroy", "opo_last_error")
-KERNEL_CLASSES = ("column_pass", "row_pass", "energy_reduce")
+KERNEL_CLASSES = ("column_pass", "row_pass", "energy_reduce", "mixed_pass")
 
 _d3 = ctypes.c_double * 3
 _i3 = ctypes.c_int32 * 3
@@ -231,8 +231,8 @@ class Opo:
 
     def kernel_times(self):
         """{kernel class: (total device ms, launches)} under the profile option."""
-        ms = np.zeros(3)
-        n = np.zeros(3, dtype=np.int64)
+        ms = np.zeros(len(KERNEL_CLASSES))
+        n = np.zeros(len(KERNEL_CLASSES), dtype=np.int64)
         _check(self._lib.opo_kernel_times(self.h, ms.ctypes.data, n.ctypes.data))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_CLASSES)}
 

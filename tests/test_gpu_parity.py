@@ -215,3 +215,34 @@ def test_full_size_sro_bench_configuration():
     for x in range(3):
         assert np.max(np.abs(e[:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E["f32"]
         assert rel_l2(got[x], ref[x]) <= 10 * TOL["f32"], (x, rel_l2(got[x], ref[x]))
+
+
+def test_mixed_schedule_batch_equals_singles_and_oracle():
+    """A batch whose sizes share one column and one row kernel runs as two halves a launch
+    apart, column tiles of one half together with row tiles of the other; every instance
+    still equals its own single-instance run bit for bit, and the oracle."""
+    say("mixed-schedule batch")
+    sizes = [8192, 4096, 16384, 4096, 8192]
+    insts = []
+    for b, nt in enumerate(sizes):
+        ins = _stress(nt, seed=40 + b)
+        ins["cavity"] = W.cavity(resonant=(0, 1, 0), refl=(0.0, 0.85 + 0.02 * b, 0.0),
+                                 delta=(0.0, -0.1 * b, 0.0), eom_beta=0.3, eom_fpm_thz=1.0 / 40.0)
+        insts.append(ins)
+    nz, nrt = 6, 3
+    with B.Opo(insts, nz, precision="f32") as hb:
+        hb.cavity_roundtrip(nrt)
+        batch = [(hb.get_fields(i), hb.energy_history(i)) for i in range(len(sizes))]
+        hb.ssfm_propagate(5, 0.1)
+        prop = [hb.get_fields(i) for i in range(len(sizes))]
+    for i, ins in enumerate(insts):
+        with _handle(ins, nz, "f32") as h:
+            h.cavity_roundtrip(nrt)
+            assert np.array_equal(batch[i][0], h.get_fields())
+            assert np.array_equal(batch[i][1], h.energy_history())
+            h.ssfm_propagate(5, 0.1)
+            assert np.array_equal(prop[i], h.get_fields())
+        ref, e_ref = oracle.roundtrips(ins["crystal"], ins["cavity"], ins["fields"], ins["pump_in"], nz, nrt)
+        for x in range(3):
+            assert rel_l2(batch[i][0][x], ref[x]) <= 10 * TOL["f32"], (i, x)
+            assert np.max(np.abs(batch[i][1][:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E["f32"]
