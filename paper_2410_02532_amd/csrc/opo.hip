@@ -145,6 +145,8 @@ struct opo_s {
     int tiles_a = 0, tiles_b = 0;
     std::vector<Group> groups_a, groups_b;   // tiles of one size range (and half)
     bool mixed = false;              // two halves a launch apart, mixed launches
+    int *d_map[2] = {nullptr, nullptr};  // workgroup -> tile maps of the two mixed launches
+    int map_len[2] = {0, 0};
     int *d_tile_a = nullptr, *d_tile_b = nullptr;
     void *d_tw = nullptr, *d_tw4 = nullptr;
     void *d_disp = nullptr;          // linear-propagator tables, one per distinct crystal/grid
@@ -307,7 +309,7 @@ static void release(opo_t *h)
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->own_state && h->state) (void)hipFree(h->state);
-    void *bufs[] = {h->pump, h->d_inst, h->d_tile_a, h->d_tile_b, h->d_tw, h->d_tw4, h->d_disp,
+    void *bufs[] = {h->pump, h->d_inst, h->d_tile_a, h->d_tile_b, h->d_tw, h->d_tw4, h->d_disp, h->d_map[0], h->d_map[1],
                     h->d_partial, h->d_hist, h->d_counter, h->scratch};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -414,13 +416,14 @@ template <typename R> static void launch_mixed(opo_t *h, StepArgs<R> a, int ch, 
     ac.step = step;
     ac.tile0 = gc.tile0;
     ac.tile_count = gc.count;
+    ac.block_map = h->d_map[ch];
     ar.tile_inst = h->d_tile_b;
     ar.flags = B_DISP;
     ar.tile0 = gr.tile0;
     ar.tile_count = gr.count;
     void *args[] = {&ac, &ar};
     prof_begin(h, OPO_K_MIXED);
-    (void)hipLaunchKernel(mixed_fn<R>(gc.ln, gr.ln), dim3(gc.count + gr.count), dim3(kThreads), args,
+    (void)hipLaunchKernel(mixed_fn<R>(gc.ln, gr.ln), dim3(h->map_len[ch]), dim3(kThreads), args,
                           std::max(h->lds_a, h->lds_b), h->stream);
     prof_end(h);
 }
@@ -697,6 +700,38 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         }
     }
 
+    // ---- workgroup -> tile maps of the mixed launches. Workgroup b runs on
+    // XCD b mod 8; row tile t of an instance goes to XCD t mod 8, column
+    // tiles are spread evenly, and within an XCD the two kinds alternate in
+    // proportion to their counts
+    std::vector<int> maps[2];
+    if (h->mixed) {
+        constexpr int kXcd = 8;
+        for (int ch = 0; ch < 2; ++ch) {
+            const Group &gc = h->groups_a[ch], &gr = h->groups_b[1 - ch];
+            std::vector<int> qc[kXcd], qr[kXcd];
+            for (int t = 0; t < gc.count; ++t) qc[t % kXcd].push_back(gc.tile0 + t);
+            for (int t = 0; t < gr.count; ++t) {
+                const int tile = gr.tile0 + t;
+                const int local = tile - h->inst[tile_b_inst[tile]].tile_b0;
+                qr[local % kXcd].push_back(tile);
+            }
+            size_t len = 0;
+            for (int x = 0; x < kXcd; ++x) len = std::max(len, qc[x].size() + qr[x].size());
+            maps[ch].assign(len * kXcd, kNoTile);
+            for (int x = 0; x < kXcd; ++x) {
+                const long long nc = static_cast<long long>(qc[x].size());
+                const long long tot = nc + static_cast<long long>(qr[x].size());
+                for (long long q = 0; q < tot; ++q) {
+                    const long long before = q * nc / tot;
+                    const bool col = (q + 1) * nc / tot > before;
+                    maps[ch][q * kXcd + x] = col ? qc[x][before] : -1 - qr[x][q - before];
+                }
+            }
+            h->map_len[ch] = static_cast<int>(maps[ch].size());
+        }
+    }
+
     // ---- device memory
     if (opt.state) {
         if (opt.state_bytes < need)
@@ -720,7 +755,9 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         hipMalloc(reinterpret_cast<void **>(&h->d_partial), h->tiles_a * 3 * sizeof(double)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_hist),
                   static_cast<size_t>(kHistChunk) * n * 3 * sizeof(double)) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void **>(&h->d_counter), sizeof(int)) != hipSuccess)
+        hipMalloc(reinterpret_cast<void **>(&h->d_counter), sizeof(int)) != hipSuccess ||
+        (h->mixed && (hipMalloc(reinterpret_cast<void **>(&h->d_map[0]), maps[0].size() * sizeof(int)) != hipSuccess ||
+                      hipMalloc(reinterpret_cast<void **>(&h->d_map[1]), maps[1].size() * sizeof(int)) != hipSuccess)))
         return bail(fail(OPO_ENOMEM, "hipMalloc of the tables failed"));
 
     h->lds_a = (opt.precision == OPO_F64 ? lds_elems<double>(static_cast<int>(max_a))
@@ -744,6 +781,8 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     if (hipMemcpyAsync(h->d_inst, h->inst.data(), n * sizeof(InstDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(h->d_tile_a, tile_a_inst.data(), tile_a_inst.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(h->d_tile_b, tile_b_inst.data(), tile_b_inst.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
+        (h->mixed && hipMemcpyAsync(h->d_map[0], maps[0].data(), maps[0].size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess) ||
+        (h->mixed && hipMemcpyAsync(h->d_map[1], maps[1].data(), maps[1].size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess) ||
         hipStreamSynchronize(st) != hipSuccess)
         return bail(fail(OPO_EDEVICE, "upload of the instance tables failed"));
     if (opt.precision == OPO_F64) upload_phasors<double>(h->d_tw, twre, twim, st);

@@ -86,6 +86,7 @@ template <typename R> struct StepArgs {
     double *partial;          // [column tiles][3] energy partial sums
     int tile0;                // first tile of this launch (tiles are grouped by shape)
     int tile_count;           // tiles of this launch
+    const int *block_map;     // mixed launches: workgroup -> tile (see mixed_pass)
     int flags;
     int step;                 // z-step j whose first half-step this launch runs
     int nz;                   // steps per pass (dz = L/nz when dz_arg <= 0)
@@ -474,25 +475,33 @@ constexpr int kRowRanges[][2] = {{0, 5}, {6, 11}, {12, 12}};
 // Mixed pass: the column tiles of one half of a batch and the row tiles of
 // the other half in one launch. The halves are a launch apart in their z-step
 // sequences, so every launch pairs the VALU-bound column work of one half
-// with the memory-latency-bound row work of the other. Workgroups alternate
-// between the two kinds in proportion to their counts, so that every CU gets
-// both.
+// with the memory-latency-bound row work of the other. The host orders the
+// workgroups so that every CU gets both kinds, and so that row tile t of
+// every instance runs on XCD t mod 8 (workgroups are dealt to the eight XCDs
+// round robin): each XCD's L2 then holds one eighth of a shared propagator
+// table instead of all of it.
+// Workgroups per CU the mixed kernel is compiled for: four (at most 128
+// VGPRs) for the FP32 shapes of up to 2^18 points, where that costs a few
+// spilled registers, else whatever the registers allow.
+template <typename R, int CR, int RR> constexpr int mixed_min_blocks() { return sizeof(R) == 4 && CR == 0 && RR <= 1 ? 4 : 1; }
+
+constexpr int kNoTile = -2147483647 - 1;
+
 template <typename R, int CR, int RR>
-__global__ __launch_bounds__(kThreads) void mixed_pass(StepArgs<R> ac, StepArgs<R> ar)
+__global__ __launch_bounds__(kThreads, (mixed_min_blocks<R, CR, RR>())) void mixed_pass(StepArgs<R> ac, StepArgs<R> ar)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ Coupling<R> cpl;
     __shared__ double red[3 * kThreads / 64];
     cplx<R> *s = reinterpret_cast<cplx<R> *>(lds_raw);
-    const long long nc = ac.tile_count, total = nc + ar.tile_count;
-    const long long b = blockIdx.x;
-    const long long before = b * nc / total;            // column tiles among blocks < b
-    if ((b + 1) * nc / total > before) {
-        const int tile = ac.tile0 + static_cast<int>(before);
-        column_dispatch<R, kColRanges[CR][0], kColRanges[CR][1]>(ac, ac.inst[ac.tile_inst[tile]], tile, s, &cpl,
+    // block -> tile map built on the host: >= 0 a column tile, < 0 row tile -1-code
+    const int code = ac.block_map[blockIdx.x];
+    if (code == kNoTile) return;
+    if (code >= 0) {
+        column_dispatch<R, kColRanges[CR][0], kColRanges[CR][1]>(ac, ac.inst[ac.tile_inst[code]], code, s, &cpl,
                                                                  red);
     } else {
-        const int tile = ar.tile0 + static_cast<int>(b - before);
+        const int tile = -1 - code;
         row_dispatch<R, kRowRanges[RR][0], kRowRanges[RR][1]>(ar, ar.inst[ar.tile_inst[tile]], tile, s);
     }
 }
