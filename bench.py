@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 from paper_2410_02532_amd import opo as B          # noqa: E402
+from paper_2410_02532_amd import traffic as T      # noqa: E402
 from paper_2410_02532_amd import workloads as W    # noqa: E402
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
@@ -81,9 +82,12 @@ def roofline(w, precision, n_rt):
     bytes_per_launch = 2 * state          # one read and one write of the three fields
     avg_s = ms / 1e3 / launches
     achieved = bytes_per_launch / avg_s / 1e9
+    # HBM bytes per launch from the counter summary of this kernel and workload,
+    # null unless it was taken on the current kernel sources
+    traffic = T.load(os.path.join(ROOT, "profiles", "%s_%s_%s_traffic.md" % (dom, w["name"], precision)))
     return {
         "bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
         "avg_launch_us": round(avg_s * 1e6, 3), "bytes_per_launch": bytes_per_launch,
         "kernel_ms": {k: round(v[0], 3) for k, v in per.items()},
         "launches": {k: v[1] for k, v in per.items()},
