@@ -31,6 +31,18 @@ from paper_2410_02532_amd import traffic as T      # noqa: E402
 from paper_2410_02532_amd import workloads as W    # noqa: E402
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
+# FP32 vector FMA issued one value per lane (the library is built without packed
+# FP32 instructions): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+VALU_PEAK_TFLOPS = 78.6
+VALU_PEAK_PACKED_TFLOPS = 157.3   # the same with packed (two-wide) FP32 FMA
+BYTES_PER_UNIT = {"f32": 48, "f64": 96}   # read + write of three complex fields
+
+
+def flops_per_unit(nt):
+    """Algorithmic flops of one field-point-step (all three fields at one time point, one
+    z-step): two RK4 half-steps (2 x 228), a forward and an inverse FFT of each field
+    (3 x 2 x 5 log2 Nt) and the dispersion multiply (3 x 6)."""
+    return 2 * 228 + 3 * 2 * 5 * np.log2(nt) + 18
 METRIC = "field-point-steps/s (Nt*Nz*round trips/s)"
 
 
@@ -66,29 +78,38 @@ def run_gpu(w, steps, warmup, precision):
 
 
 def roofline(w, precision, n_rt):
-    """Per-kernel device time from event pairs around every launch (profile option)."""
+    """Roofline of the dominant kernel from per-launch device times (HIP events around every
+    launch, profile option).
+
+    Each column, row or mixed launch carries out half of a z-step for the points it covers
+    (a z-step is a column and a row pass of every instance), so its algorithmic work is half
+    a field-point-step per covered point: 48/2 B and flops_per_unit/2 in FP32. The kernels
+    issue more VALU work per byte than the FP32 ridge of the non-packed vector units, so the
+    binding roofline is the ALU one; the HBM figure is reported beside it."""
     with B.from_workload(w, precision=precision, profile=True) as h:
         h.cavity_roundtrip(2)            # warm up
         before = h.kernel_times()
         h.cavity_roundtrip(n_rt)
         after = h.kernel_times()
     per = {k: (after[k][0] - before[k][0], after[k][1] - before[k][1]) for k in after}
-    # the dominant launch class; a column, row or mixed launch each reads and
-    # writes the three fields of every instance it covers once
     dom = max(("column_pass", "row_pass", "mixed_pass"), key=lambda k: per[k][0])
     ms, launches = per[dom]
-    elem = 16 if precision == "f64" else 8
-    state = sum(3 * ins["crystal"]["nt"] * elem for ins in instances_of(w))
-    bytes_per_launch = 2 * state          # one read and one write of the three fields
+    nts = [ins["crystal"]["nt"] for ins in instances_of(w)]
+    bytes_per_launch = BYTES_PER_UNIT[precision] * sum(nts) / 2
+    flops_per_launch = sum(nt * flops_per_unit(nt) for nt in nts) / 2
     avg_s = ms / 1e3 / launches
-    achieved = bytes_per_launch / avg_s / 1e9
+    tflops = flops_per_launch / avg_s / 1e12
+    gbs = bytes_per_launch / avg_s / 1e9
     # HBM bytes per launch from the counter summary of this kernel and workload,
     # null unless it was taken on the current kernel sources
     traffic = T.load(os.path.join(ROOT, "profiles", "%s_%s_%s_traffic.md" % (dom, w["name"], precision)))
     return {
-        "bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-        "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-        "avg_launch_us": round(avg_s * 1e6, 3), "bytes_per_launch": bytes_per_launch,
+        "bound": "alu", "kernel": dom, "achieved": round(tflops, 3), "peak": VALU_PEAK_TFLOPS,
+        "unit": "TFLOP/s", "frac": round(tflops / VALU_PEAK_TFLOPS, 5), "traffic": traffic,
+        "flops_per_launch": round(flops_per_launch), "avg_launch_us": round(avg_s * 1e6, 3),
+        "frac_of_packed_peak": round(tflops / VALU_PEAK_PACKED_TFLOPS, 5),
+        "hbm": {"achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 5), "bytes_per_launch": round(bytes_per_launch)},
         "kernel_ms": {k: round(v[0], 3) for k, v in per.items()},
         "launches": {k: v[1] for k, v in per.items()},
     }

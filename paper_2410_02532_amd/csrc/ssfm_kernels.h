@@ -271,15 +271,12 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
         coupling_tile<R>(d, zb + (a.step - 1) * dz + 0.5 * dz, zb + a.step * dz, dz, cpl);
 
     V v[3][PF];
-    Phasor<R> w4[PF];
-    const bool tw_needed = (flags & (A_INV | A_FWD)) && N > 1;
-    if (tw_needed) {
-        const double2 *t4 = a.tw4 + d.tw4_off;
-#pragma unroll
-        for (int m = 0; m < PF; ++m)
-            w4[m] = twiddle4<R>(t4, d.tw4_bits,
-                                (static_cast<unsigned>(j1) * static_cast<unsigned>(t + m * T)) & (nt - 1));
-    }
+    // four-step twiddle W_nt^{j1 k2} of sample m; formed where it is used (before
+    // the inverse and after the forward column FFT) rather than held in registers
+    const double2 *t4 = a.tw4 + d.tw4_off;
+    auto w4 = [&](int m) {
+        return twiddle4<R>(t4, d.tw4_bits, (static_cast<unsigned>(j1) * static_cast<unsigned>(t + m * T)) & (nt - 1));
+    };
 #pragma unroll
     for (int f = 0; f < 3; ++f)
 #pragma unroll
@@ -291,10 +288,11 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     if (flags & A_INV) {
         if constexpr (N > 1) {
 #pragma unroll
-            for (int f = 0; f < 3; ++f)
+            for (int m = 0; m < PF; ++m) {
+                const Phasor<R> w = w4(m);
 #pragma unroll
-                for (int m = 0; m < PF; ++m)
-                    v[f][m] = pmul<true>(v[f][m], w4[m]);
+                for (int f = 0; f < 3; ++f) v[f][m] = pmul<true>(v[f][m], w);
+            }
         }
         reg_fft<R, N, PF, 3, +1, COLS>(v, s, base, t, a.tw);
     }
@@ -355,10 +353,11 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
         reg_fft<R, N, PF, 3, -1, COLS>(v, s, base, t, a.tw);
         if constexpr (N > 1) {
 #pragma unroll
-            for (int f = 0; f < 3; ++f)
+            for (int m = 0; m < PF; ++m) {
+                const Phasor<R> w = w4(m);
 #pragma unroll
-                for (int m = 0; m < PF; ++m)
-                    v[f][m] = pmul(v[f][m], w4[m]);
+                for (int f = 0; f < 3; ++f) v[f][m] = pmul(v[f][m], w);
+            }
         }
     }
     if (act) {
@@ -481,8 +480,8 @@ constexpr int kRowRanges[][2] = {{0, 5}, {6, 11}, {12, 12}};
 // round robin): each XCD's L2 then holds one eighth of a shared propagator
 // table instead of all of it.
 // Workgroups per CU the mixed kernel is compiled for: four (at most 128
-// VGPRs) for the FP32 shapes of up to 2^18 points, where that costs a few
-// spilled registers, else whatever the registers allow.
+// VGPRs) for FP32 columns of up to 64 points, which fit that without spills,
+// else whatever the registers allow.
 template <typename R, int CR, int RR> constexpr int mixed_min_blocks() { return sizeof(R) == 4 && CR == 0 && RR <= 1 ? 4 : 1; }
 
 constexpr int kNoTile = -2147483647 - 1;
