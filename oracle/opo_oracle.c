@@ -18,6 +18,7 @@
  *   Eq. 6      resonant-field boundary condition            -> ora_roundtrips
  *   Sec. 2.3   intracavity GDD and EOM                      -> ora_gdd, ora_eom
  *   Sec. 4.1   main loop: pump read, pass, GDD, phase, EOM  -> ora_roundtrips
+ *   Sec. 2.4   degenerate signal equation (two waves)        -> cwe2_rhs
  *
  * Readings of passages the paper leaves open (each one is also recorded in
  * the design notes):
@@ -37,6 +38,13 @@
  *     pump and non-resonant signal/idler start at zero; after the pass the
  *     energies sum_j |A_x(t_j)|^2 are recorded, then GDD, then
  *     sqrt(R_x) e^{i delta_x} on resonant fields, then the EOM phase.
+ *   - Two coupled waves (degenerate operation, signal = idler; nf = 2): the
+ *     paper gives the signal equation dA_s/dz = i kappa_s A_p A_s^* (with
+ *     e^{+i dk z}) and leaves the pump equation unprinted. We take
+ *     dA_p/dz = i kappa_p2 A_s^2 e^{-i dk z} with kappa_p2 = 2 pi d_eff /
+ *     (n_p lambda_s), the coefficient for which n_p|A_p|^2 + n_s|A_s|^2 is
+ *     conserved (kappa_p/2 at lambda_s = 2 lambda_p). Fields are then stored
+ *     as pump, signal; the idler entries of the parameters are unused.
  *
  * Units: t [ps], z [mm], omega [rad/ps], lambda [um], d_eff [pm/V],
  * dk [1/mm], alpha [1/mm], db1 [ps/mm], b2 [fs^2/mm], b3 [fs^3/mm],
@@ -54,6 +62,7 @@ typedef double complex cplx;
 
 typedef struct {
     int nt;                /* time points, a power of two                 */
+    int nf;                /* coupled waves: 3 (p, s, i) or 2 (p, s)      */
     double t_window_ps;    /* T: time window = round-trip time slice        */
     double length_mm;      /* crystal length L                              */
     double lambda_um[3];   /* pump, signal, idler wavelengths               */
@@ -141,11 +150,16 @@ double ora_omega(int k, int n, double t_window_ps)
 }
 
 /* Nonlinear coupling, Sec. 2.1: kappa_x = 2 pi d_eff / (n_x lambda_x).
- * pm/V over um gives 1e-6 per metre; 1e-3 more converts to per mm. */
+ * pm/V over um gives 1e-6 per metre; 1e-3 more converts to per mm.
+ * Two waves: (kappa_p2, kappa_s, 0), kappa_p2 = 2 pi d_eff / (n_p lambda_s). */
 void ora_kappa(const ora_crystal *c, double kappa[3])
 {
     for (int x = 0; x < 3; x++)
         kappa[x] = 2.0 * ORA_PI * c->deff_pm_per_v / (c->n[x] * c->lambda_um[x]) * 1e-9;
+    if (c->nf == 2) {
+        kappa[0] = 2.0 * ORA_PI * c->deff_pm_per_v / (c->n[0] * c->lambda_um[1]) * 1e-9;
+        kappa[2] = 0.0;
+    }
 }
 
 /* Frequency-domain propagator of Eq. 5 (reading above) over a step dz. */
@@ -171,30 +185,48 @@ static void cwe_rhs(const double kap[3], cplx ph, cplx ap, cplx as, cplx ai, cpl
     out[2] = I * kap[2] * ap * conj(as) * ph;
 }
 
+/* The two-wave (degenerate) right-hand side: pump and signal. */
+static void cwe2_rhs(const double kap[3], cplx ph, cplx ap, cplx as, cplx out[3])
+{
+    out[0] = I * kap[0] * as * as * conj(ph);
+    out[1] = I * kap[1] * ap * conj(as) * ph;
+    out[2] = 0.0;
+}
+
+static void rhs(int nf, const double kap[3], cplx ph, const cplx y[3], cplx out[3])
+{
+    if (nf == 2)
+        cwe2_rhs(kap, ph, y[0], y[1], out);
+    else
+        cwe_rhs(kap, ph, y[0], y[1], y[2], out);
+}
+
 /* One classical RK4 step of size h from z0 for all time points of the
- * three fields stored as A[x*nt + j]. */
+ * nf fields stored as A[x*nt + j]. */
 void ora_rk4(const ora_crystal *c, cplx *a, double z0, double h)
 {
-    int n = c->nt;
+    int n = c->nt, nf = c->nf;
     double kap[3];
     ora_kappa(c, kap);
     cplx ph0 = cexp(I * c->dk_per_mm * z0);
     cplx ph1 = cexp(I * c->dk_per_mm * (z0 + 0.5 * h));
     cplx ph2 = cexp(I * c->dk_per_mm * (z0 + h));
     for (int j = 0; j < n; j++) {
-        cplx y[3] = {a[j], a[n + j], a[2 * n + j]};
+        cplx y[3] = {0.0, 0.0, 0.0};
+        for (int x = 0; x < nf; x++)
+            y[x] = a[x * n + j];
         cplx k1[3], k2[3], k3[3], k4[3], t[3];
-        cwe_rhs(kap, ph0, y[0], y[1], y[2], k1);
+        rhs(nf, kap, ph0, y, k1);
         for (int x = 0; x < 3; x++)
             t[x] = y[x] + 0.5 * h * k1[x];
-        cwe_rhs(kap, ph1, t[0], t[1], t[2], k2);
+        rhs(nf, kap, ph1, t, k2);
         for (int x = 0; x < 3; x++)
             t[x] = y[x] + 0.5 * h * k2[x];
-        cwe_rhs(kap, ph1, t[0], t[1], t[2], k3);
+        rhs(nf, kap, ph1, t, k3);
         for (int x = 0; x < 3; x++)
             t[x] = y[x] + h * k3[x];
-        cwe_rhs(kap, ph2, t[0], t[1], t[2], k4);
-        for (int x = 0; x < 3; x++)
+        rhs(nf, kap, ph2, t, k4);
+        for (int x = 0; x < nf; x++)
             a[x * n + j] = y[x] + h / 6.0 * (k1[x] + 2.0 * k2[x] + 2.0 * k3[x] + k4[x]);
     }
 }
@@ -209,13 +241,13 @@ static void linear_with(cplx *field, int n, const cplx *h, const cplx *w)
     fft_with(field, n, 1, w);
 }
 
-/* e^{L_x dz} for the three fields: FFT, multiply by H_x, inverse FFT. */
+/* e^{L_x dz} for the nf fields: FFT, multiply by H_x, inverse FFT. */
 void ora_linear(const ora_crystal *c, cplx *a, double dz)
 {
     int n = c->nt;
     cplx *w = twiddles(n);
     cplx *h = malloc(sizeof(cplx) * (size_t)n);
-    for (int x = 0; x < 3; x++) {
+    for (int x = 0; x < c->nf; x++) {
         ora_dispersion(c, x, dz, h);
         linear_with(a + (size_t)x * n, n, h, w);
     }
@@ -232,12 +264,12 @@ void ora_pass(const ora_crystal *c, cplx *a, int nz, double dz, double z0)
     int n = c->nt;
     cplx *w = twiddles(n);
     cplx *h = malloc(sizeof(cplx) * (size_t)n * 3);
-    for (int x = 0; x < 3; x++)
+    for (int x = 0; x < c->nf; x++)
         ora_dispersion(c, x, dz, h + (size_t)x * n);
     for (int j = 0; j < nz; j++) {
         double zj = z0 + (double)j * dz;
         ora_rk4(c, a, zj, 0.5 * dz);
-        for (int x = 0; x < 3; x++)
+        for (int x = 0; x < c->nf; x++)
             linear_with(a + (size_t)x * n, n, h + (size_t)x * n, w);
         ora_rk4(c, a, zj + 0.5 * dz, 0.5 * dz);
     }
@@ -252,11 +284,11 @@ void ora_pass_unsym(const ora_crystal *c, cplx *a, int nz, double dz, double z0)
     int n = c->nt;
     cplx *w = twiddles(n);
     cplx *h = malloc(sizeof(cplx) * (size_t)n * 3);
-    for (int x = 0; x < 3; x++)
+    for (int x = 0; x < c->nf; x++)
         ora_dispersion(c, x, dz, h + (size_t)x * n);
     for (int j = 0; j < nz; j++) {
         ora_rk4(c, a, z0 + (double)j * dz, dz);
-        for (int x = 0; x < 3; x++)
+        for (int x = 0; x < c->nf; x++)
             linear_with(a + (size_t)x * n, n, h + (size_t)x * n, w);
     }
     free(h);
@@ -293,7 +325,8 @@ void ora_eom(cplx *field, int n, double t_window_ps, double beta, double fpm_thz
 /* ----------------------------------------------------- round trips -- */
 
 /* n_rt cavity round trips (Sec. 4.1 main loop with Eq. 6). energy[m*3+x]
- * receives sum_j |A_x(t_j)|^2 after the crystal pass of round trip m.
+ * receives sum_j |A_x(t_j)|^2 after the crystal pass of round trip m (0 for
+ * x >= nf).
  * pump_in: nt input-pump samples read into a non-resonant pump at the
  * start of every round trip. */
 void ora_roundtrips(const ora_crystal *c, const ora_cavity *cav, cplx *a,
@@ -304,7 +337,7 @@ void ora_roundtrips(const ora_crystal *c, const ora_cavity *cav, cplx *a,
     for (int m = 0; m < n_rt; m++) {
         if (!cav->resonant[0])
             memcpy(a, pump_in, sizeof(cplx) * (size_t)n);
-        for (int x = 1; x < 3; x++)
+        for (int x = 1; x < c->nf; x++)
             if (!cav->resonant[x])
                 memset(a + (size_t)x * n, 0, sizeof(cplx) * (size_t)n);
 
@@ -312,22 +345,26 @@ void ora_roundtrips(const ora_crystal *c, const ora_cavity *cav, cplx *a,
 
         for (int x = 0; x < 3; x++) {
             double e = 0.0;
+            if (x >= c->nf) {
+                energy[m * 3 + x] = 0.0;
+                continue;
+            }
             for (int j = 0; j < n; j++) {
                 cplx v = a[(size_t)x * n + j];
                 e += creal(v) * creal(v) + cimag(v) * cimag(v);
             }
             energy[m * 3 + x] = e;
         }
-        for (int x = 0; x < 3; x++)
+        for (int x = 0; x < c->nf; x++)
             if (cav->gdd_on[x] && cav->gdd_fs2 != 0.0)
                 ora_gdd(a + (size_t)x * n, n, c->t_window_ps, cav->gdd_fs2);
-        for (int x = 0; x < 3; x++)
+        for (int x = 0; x < c->nf; x++)
             if (cav->resonant[x]) {
                 cplx f = sqrt(cav->refl[x]) * cexp(I * cav->delta_rad[x]);
                 for (int j = 0; j < n; j++)
                     a[(size_t)x * n + j] *= f;
             }
-        for (int x = 0; x < 3; x++)
+        for (int x = 0; x < c->nf; x++)
             if (cav->eom_on[x] && cav->eom_beta != 0.0)
                 ora_eom(a + (size_t)x * n, n, c->t_window_ps, cav->eom_beta, cav->eom_fpm_thz);
     }

@@ -1,8 +1,10 @@
 """ctypes front end of the FP64 C oracle (``opo_oracle.c``).
 
 Test infrastructure only. Every function takes and returns numpy complex128
-arrays; fields are stacked as ``a[x, j]`` with x = 0 pump, 1 signal, 2 idler.
-Parameters come as plain dicts (keys as in :class:`Crystal` / :class:`Cavity`).
+arrays; fields are stacked as ``a[x, j]`` with x = 0 pump, 1 signal, 2 idler
+(three coupled waves) or x = 0 pump, 1 signal (two waves, crystal key
+``nf`` = 2). Parameters come as plain dicts (keys as in :class:`Crystal` /
+:class:`Cavity`; ``nf`` defaults to 3).
 """
 import ctypes
 import os
@@ -21,6 +23,7 @@ _i3 = ctypes.c_int * 3
 class Crystal(ctypes.Structure):
     _fields_ = [
         ("nt", ctypes.c_int),
+        ("nf", ctypes.c_int),
         ("t_window_ps", ctypes.c_double),
         ("length_mm", ctypes.c_double),
         ("lambda_um", _c3),
@@ -37,7 +40,7 @@ class Crystal(ctypes.Structure):
     def from_dict(cls, d):
         c = cls()
         for name, ctype in cls._fields_:
-            v = d[name]
+            v = d.get(name, 3) if name == "nf" else d[name]
             if ctype in (_c3,):
                 setattr(c, name, _c3(*[float(x) for x in v]))
             elif ctype is ctypes.c_int:
@@ -118,10 +121,18 @@ def _cplx(a):
     return np.ascontiguousarray(a, dtype=np.complex128).copy()
 
 
-def _fields(a, nt):
+def _nf(crystal):
+    nf = int(crystal.get("nf", 3))
+    if nf not in (2, 3):
+        raise ValueError("nf must be 2 or 3")
+    return nf
+
+
+def _fields(a, crystal):
     a = _cplx(a)
-    if a.shape != (3, nt):
-        raise ValueError("fields must have shape (3, %d), got %s" % (nt, a.shape))
+    shape = (_nf(crystal), crystal["nt"])
+    if a.shape != shape:
+        raise ValueError("fields must have shape %s, got %s" % (shape, a.shape))
     return a
 
 
@@ -157,27 +168,27 @@ def dispersion(crystal, field, dz):
 
 
 def rk4(crystal, a, z0, h):
-    a = _fields(a, crystal["nt"])
+    a = _fields(a, crystal)
     _load().ora_rk4(ctypes.byref(Crystal.from_dict(crystal)), _ptr(a), z0, h)
     return a
 
 
 def linear(crystal, a, dz):
-    a = _fields(a, crystal["nt"])
+    a = _fields(a, crystal)
     _load().ora_linear(ctypes.byref(Crystal.from_dict(crystal)), _ptr(a), dz)
     return a
 
 
 def ssfm_pass(crystal, a, nz, dz, z0=0.0):
     """nz symmetrized SSFM steps of size dz starting at z0; returns new fields."""
-    a = _fields(a, crystal["nt"])
+    a = _fields(a, crystal)
     _load().ora_pass(ctypes.byref(Crystal.from_dict(crystal)), _ptr(a), int(nz), float(dz),
                      float(z0))
     return a
 
 
 def ssfm_pass_unsym(crystal, a, nz, dz, z0=0.0):
-    a = _fields(a, crystal["nt"])
+    a = _fields(a, crystal)
     _load().ora_pass_unsym(ctypes.byref(Crystal.from_dict(crystal)), _ptr(a), int(nz),
                            float(dz), float(z0))
     return a
@@ -196,9 +207,10 @@ def eom(field, t_window_ps, beta, fpm_thz):
 
 
 def roundtrips(crystal, cavity, a, pump_in, nz, n_rt):
-    """n_rt cavity round trips. Returns (fields, energies[n_rt, 3])."""
+    """n_rt cavity round trips. Returns (fields, energies[n_rt, 3]); the idler column is
+    zero for two waves."""
     nt = crystal["nt"]
-    a = _fields(a, nt)
+    a = _fields(a, crystal)
     p = _cplx(np.broadcast_to(np.asarray(pump_in, dtype=np.complex128), (nt,)))
     e = np.zeros((int(n_rt), 3))
     _load().ora_roundtrips(ctypes.byref(Crystal.from_dict(crystal)),
