@@ -35,14 +35,19 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, 8 TB/s
 # FP32 instructions): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
 VALU_PEAK_TFLOPS = 78.6
 VALU_PEAK_PACKED_TFLOPS = 157.3   # the same with packed (two-wide) FP32 FMA
-BYTES_PER_UNIT = {"f32": 48, "f64": 96}   # read + write of three complex fields
+BYTES_PER_FIELD = {"f32": 16, "f64": 32}   # read + write of one complex field
 
 
-def flops_per_unit(nt):
-    """Algorithmic flops of one field-point-step (all three fields at one time point, one
-    z-step): two RK4 half-steps (2 x 228), a forward and an inverse FFT of each field
-    (3 x 2 x 5 log2 Nt) and the dispersion multiply (3 x 6)."""
-    return 2 * 228 + 3 * 2 * 5 * np.log2(nt) + 18
+def nf_of(ins):
+    return int(ins["crystal"].get("nf", 3))
+
+
+def flops_per_unit(nt, nf=3):
+    """Algorithmic flops of one field-point-step (all nf fields at one time point, one
+    z-step): two RK4 half-steps (2 x 228 for three waves, two thirds of it for two), a
+    forward and an inverse FFT of each field (nf x 2 x 5 log2 Nt) and the dispersion
+    multiply (nf x 6)."""
+    return 2 * 228 * nf / 3 + nf * 2 * 5 * np.log2(nt) + 6 * nf
 METRIC = "field-point-steps/s (Nt*Nz*round trips/s)"
 
 
@@ -94,9 +99,9 @@ def roofline(w, precision, n_rt):
     per = {k: (after[k][0] - before[k][0], after[k][1] - before[k][1]) for k in after}
     dom = max(("column_pass", "row_pass", "mixed_pass"), key=lambda k: per[k][0])
     ms, launches = per[dom]
-    nts = [ins["crystal"]["nt"] for ins in instances_of(w)]
-    bytes_per_launch = BYTES_PER_UNIT[precision] * sum(nts) / 2
-    flops_per_launch = sum(nt * flops_per_unit(nt) for nt in nts) / 2
+    insts = instances_of(w)
+    bytes_per_launch = sum(BYTES_PER_FIELD[precision] * nf_of(i) * i["crystal"]["nt"] for i in insts) / 2
+    flops_per_launch = sum(i["crystal"]["nt"] * flops_per_unit(i["crystal"]["nt"], nf_of(i)) for i in insts) / 2
     avg_s = ms / 1e3 / launches
     tflops = flops_per_launch / avg_s / 1e12
     gbs = bytes_per_launch / avg_s / 1e9
@@ -219,6 +224,13 @@ def main():
             d, _ = run_gpu(ws, n, 10, prec)
             var["%s_single_sro_cw_2^14" % prec] = {"value": pt_steps_per_rt(ws) * n / d,
                                                   "round_trips": n, "ms_per_step": d * 1e3 / n}
+        # the two-wave (degenerate) model over the same size mix
+        ws = W.config("degenerate_sweep")
+        n = 100
+        d, _ = run_gpu(ws, n, 5, "f32")
+        var["f32_degenerate_sweep"] = {"value": pt_steps_per_rt(ws) * n / d, "round_trips": n,
+                                       "ms_per_step": d * 1e3 / n, "instances": len(ws["instances"]),
+                                       "fields": 2}
         line["variants"] = var
         print("variants: %s" % json.dumps(var), file=sys.stderr, flush=True)
 

@@ -2,7 +2,8 @@
  * opo.h -- C ABI of the MI355X (gfx950) optical parametric oscillator hot path.
  *
  * The library propagates the three-wave coupled-wave equations (Eqs. 2-4 of
- * arXiv 2410.02532) for pump (p, index 0), signal (s, 1) and idler (i, 2)
+ * arXiv 2410.02532) for pump (p, index 0), signal (s, 1) and idler (i, 2), or
+ * at degeneracy the two-wave equations for pump and signal (see n_fields),
  * through a chi(2) crystal with the fixed-step symmetrized split-step Fourier
  * method (Sec. 2.2, Eqs. 10-11: nonlinear half-step by RK4, linear step in
  * the frequency domain, nonlinear half-step), and repeats the pass over cavity
@@ -23,6 +24,12 @@
  *     the group-delay mismatch to the signal (a positive value is slower and
  *     drifts to later t). The phase is formed and reduced modulo 2 pi in FP64.
  *   - Coupling (Sec. 2.1): kappa_x = 2 pi d_eff/(n_x lambda_x).
+ *   - Two waves (degenerate operation, signal = idler): dA_s/dz =
+ *     i kappa_s A_p A_s^* e^{+i dk z}, the signal equation of the paper's
+ *     degenerate case (Sec. 2.4), and dA_p/dz = i kappa_p2 A_s^2 e^{-i dk z}
+ *     with kappa_p2 = 2 pi d_eff/(n_p lambda_s), the pump coefficient that
+ *     conserves n_p|A_p|^2 + n_s|A_s|^2 (the paper does not print it). The
+ *     idler entries of every per-field array are then unused.
  *   - Host field arrays are interleaved complex128: re, im, re, im, ...
  *   - Every call returns an opo_status; negative values are errors and
  *     opo_last_error() returns a message for the calling thread. No C++
@@ -57,12 +64,14 @@ typedef struct {
     double t_window_ps;     /* window T (> 0)                                     */
     double lambda_um[3];    /* wavelengths p, s, i (> 0)                          */
     double n[3];            /* refractive indices (> 0)                           */
-    const double *init;     /* 3*nt complex128 initial fields p, s, i (time
-                               domain), host memory, copied; NULL = all zero      */
+    const double *init;     /* n_fields*nt complex128 initial fields p, s(, i)
+                               (time domain), host memory, copied; NULL = zero    */
     const double *pump_in;  /* nt complex128 input pump read into a non-resonant
                                pump at the start of every round trip; NULL = the
                                constant pump_cw below                             */
     double pump_cw[2];      /* constant input pump (re, im) when pump_in is NULL  */
+    int32_t n_fields;       /* coupled waves: 3 (or 0) = pump, signal, idler;
+                               2 = pump and degenerate signal                     */
 } opo_fields_t;
 
 /* Crystal: length, z-grid and the coefficients of Eqs. 2-5. */
@@ -116,7 +125,8 @@ typedef struct {
                                trip); read with opo_kernel_times                  */
 } opo_options_t;
 
-/* Device bytes of field state for n instances (fields[i].nt) at a precision. */
+/* Device bytes of field state for n instances (n_fields * nt complex values
+ * each) at a precision. */
 uint64_t opo_state_bytes(int32_t n, const opo_fields_t *fields, int32_t precision);
 
 /* Create a handle for one OPO instance: validates every parameter (nt a power
@@ -151,7 +161,7 @@ int cavity_roundtrip(opo_t *h, int32_t n_rt);
 /* Wait for all work queued on the handle's stream. */
 int opo_sync(opo_t *h);
 
-/* Copy field `field` (0 p, 1 s, 2 i) of instance `inst` to/from host memory
+/* Copy field `field` (0 p, 1 s, 2 i; < n_fields) of instance `inst` to/from host memory
  * as nt interleaved complex128 values. domain 0 = time samples A(t_j);
  * domain 1 (get only) = unnormalized DFT sum_j A(t_j) e^{-2 pi i jk/nt} in
  * natural bin order. set also resets the instance's z to 0. */
@@ -159,8 +169,9 @@ int opo_get_fields(opo_t *h, int32_t inst, int32_t field, int32_t domain, double
 int opo_set_fields(opo_t *h, int32_t inst, int32_t field, const double *in);
 
 /* Energy history: out receives min(capacity, rows) rows of 3 doubles
- * sum_j |A_x(t_j)|^2 (p, s, i) after each pass of cavity_roundtrip, oldest
- * first; *rows receives the number recorded so far. */
+ * sum_j |A_x(t_j)|^2 (p, s, i; the idler entry is 0 for two waves) after each
+ * pass of cavity_roundtrip, oldest first; *rows receives the number recorded
+ * so far. */
 int opo_get_energy_history(opo_t *h, int32_t inst, double *out, int32_t capacity,
                            int32_t *rows);
 

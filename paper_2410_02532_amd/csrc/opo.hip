@@ -191,6 +191,23 @@ static bool finite3(const double *v)
     return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
 }
 
+// Coupled waves of an instance: 3 (pump, signal, idler; n_fields 0 or 3) or 2
+// (pump and degenerate signal).
+static int nfields(const opo_fields_t &f) { return f.n_fields == 2 ? 2 : 3; }
+
+// Coupling coefficients (Sec. 2.1, kappa_x = 2 pi d_eff/(n_x lambda_x)) in
+// 1/mm per V/m (pm/V over um, then per mm). Two waves: the signal keeps
+// kappa_s; the pump takes 2 pi d_eff/(n_p lambda_s), which conserves
+// n_p|A_p|^2 + n_s|A_s|^2 (kappa_p/2 at lambda_s = 2 lambda_p).
+static void coupling(const opo_fields_t &f, double deff, double kappa[3])
+{
+    for (int x = 0; x < 3; ++x) kappa[x] = kTwoPi * deff / (f.n[x] * f.lambda_um[x]) * 1e-9;
+    if (nfields(f) == 2) {
+        kappa[0] = kTwoPi * deff / (f.n[0] * f.lambda_um[1]) * 1e-9;
+        kappa[2] = 0.0;
+    }
+}
+
 static int validate(int n, const opo_fields_t *f, const opo_crystal_t *c, const opo_cavity_t *k,
                     int precision)
 {
@@ -203,7 +220,10 @@ static int validate(int n, const opo_fields_t *f, const opo_crystal_t *c, const 
                                         std::to_string(max_log2) + "]");
         if (!(f[i].t_window_ps > 0.0) || !std::isfinite(f[i].t_window_ps))
             return fail(OPO_EINVAL, at + "t_window_ps must be finite and > 0");
-        for (int x = 0; x < 3; ++x)
+        if (f[i].n_fields != 0 && f[i].n_fields != 2 && f[i].n_fields != 3)
+            return fail(OPO_EINVAL, at + "n_fields must be 2, 3 or 0 (= 3)");
+        const int nf = nfields(f[i]);
+        for (int x = 0; x < nf; ++x)
             if (!(f[i].lambda_um[x] > 0.0) || !std::isfinite(f[i].lambda_um[x]) ||
                 !(f[i].n[x] > 0.0) || !std::isfinite(f[i].n[x]))
                 return fail(OPO_EINVAL, at + "wavelengths and indices must be finite and > 0");
@@ -229,15 +249,16 @@ static int validate(int n, const opo_fields_t *f, const opo_crystal_t *c, const 
         // kappa |A| dz, must stay well below one
         double amax = std::hypot(f[i].pump_cw[0], f[i].pump_cw[1]);
         if (f[i].init)
-            for (long long q = 0; q < 3LL * nt; ++q)
+            for (long long q = 0; q < static_cast<long long>(nf) * nt; ++q)
                 amax = std::max(amax, std::hypot(f[i].init[2 * q], f[i].init[2 * q + 1]));
         if (f[i].pump_in)
             for (long long q = 0; q < nt; ++q)
                 amax = std::max(amax, std::hypot(f[i].pump_in[2 * q], f[i].pump_in[2 * q + 1]));
         if (!std::isfinite(amax)) return fail(OPO_EINVAL, at + "initial fields must be finite");
-        double kmax = 0.0;
-        for (int x = 0; x < 3; ++x)
-            kmax = std::max(kmax, std::fabs(kTwoPi * c[i].deff_pm_per_v / (f[i].n[x] * f[i].lambda_um[x]) * 1e-9));
+        double kap[3], kmax = 0.0;
+        coupling(f[i], c[i].deff_pm_per_v, kap);
+        for (int x = 0; x < nf; ++x)
+            kmax = std::max(kmax, std::fabs(kap[x]));
         const double step = kmax * amax * c[i].length_mm / c[i].nz;
         if (!(step < 0.5))
             return fail(OPO_EINVAL, at + "step too large for the field amplitudes (kappa |A| dz = " +
@@ -556,17 +577,18 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         d.log2n2 = p.log2n2;
         d.cols = p.cols;
         d.rows = p.rows;
+        d.nf = nfields(f[i]);
         d.off = off;
-        off += 3LL * d.nt;
+        off += static_cast<long long>(d.nf) * d.nt;
         d.pump_off = -1;
         if (f[i].pump_in) {
             d.pump_off = pump_elems;
             pump_elems += d.nt;
         }
         d.tiles_a = (d.n1 + d.cols - 1) / d.cols;
-        d.tiles_b = 3 * ((d.n2 + d.rows - 1) / d.rows);
-        // LDS of a tile: three fields of `cols` columns, or `rows` rows
-        max_a = std::max(max_a, static_cast<size_t>(3) * d.cols * d.n2);
+        d.tiles_b = d.nf * ((d.n2 + d.rows - 1) / d.rows);
+        // LDS of a tile: nf fields of `cols` columns, or `rows` rows
+        max_a = std::max(max_a, static_cast<size_t>(d.nf) * d.cols * d.n2);
         max_b = std::max(max_b, static_cast<size_t>(d.rows) * d.n1);
         // shapes the kernels are instantiated for
         const int max_ln1 = opt.precision == OPO_F64 ? kMaxLog2N1<double> : kMaxLog2N1<float>;
@@ -582,7 +604,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         build_twiddles_rows(t4re, t4im, d.nt, d.nt >> bits, static_cast<double>(1LL << bits));
 
         int res = 0, gdd = 0, eom = 0;
-        for (int x = 0; x < 3; ++x) {
+        for (int x = 0; x < d.nf; ++x) {
             if (k[i].resonant[x]) res |= 1 << x;
             if (k[i].gdd_on[x] && k[i].gdd_fs2 != 0.0) gdd |= 1 << x;
             if (k[i].eom_on[x] && k[i].eom_beta != 0.0) eom |= 1 << x;
@@ -595,9 +617,8 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
 
         const double T = f[i].t_window_ps;
         d.length_mm = c[i].length_mm;
+        coupling(f[i], c[i].deff_pm_per_v, d.kappa);
         for (int x = 0; x < 3; ++x) {
-            // Sec. 2.1: kappa = 2 pi d_eff/(n lambda); pm/V over um, then per mm
-            d.kappa[x] = kTwoPi * c[i].deff_pm_per_v / (f[i].n[x] * f[i].lambda_um[x]) * 1e-9;
             // Eq. 5 phase per mm in revolutions for bin ks (w = 2 pi ks/T):
             // (-db1 w + b2 w^2/2 - b3 w^3/6)/(2 pi)
             const double b2 = c[i].b2_fs2_per_mm[x] * 1e-6, b3 = c[i].b3_fs3_per_mm[x] * 1e-9;
@@ -627,7 +648,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         int same = -1;
         for (int o : h->disp_owner) {
             const InstDesc &e = h->inst[o];
-            if (e.nt == d.nt && e.length_mm == d.length_mm &&
+            if (e.nt == d.nt && e.nf == d.nf && e.length_mm == d.length_mm &&
                 std::memcmp(e.disp, d.disp, sizeof(d.disp)) == 0 &&
                 std::memcmp(e.alpha_half, d.alpha_half, sizeof(d.alpha_half)) == 0) {
                 same = o;
@@ -638,7 +659,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
             d.disp_off = h->inst[same].disp_off;
         } else {
             d.disp_off = disp_elems;
-            disp_elems += 3LL * d.nt;
+            disp_elems += static_cast<long long>(d.nf) * d.nt;
             h->disp_owner.push_back(i);
         }
     }
@@ -792,13 +813,14 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     for (int i = 0; i < n; ++i) {
         const InstDesc &d = h->inst[i];
         const double *src = f[i].init;
+        const long long count = static_cast<long long>(d.nf) * d.nt;
         if (!src) {
-            zeros.assign(6 * static_cast<size_t>(d.nt), 0.0);
+            zeros.assign(2 * static_cast<size_t>(count), 0.0);
             src = zeros.data();
         }
         char *dst = static_cast<char *>(h->state) + d.off * es;
-        if (opt.precision == OPO_F64) host_to_state<double>(dst, src, 3LL * d.nt, st);
-        else host_to_state<float>(dst, src, 3LL * d.nt, st);
+        if (opt.precision == OPO_F64) host_to_state<double>(dst, src, count, st);
+        else host_to_state<float>(dst, src, count, st);
         if (f[i].pump_in) {
             char *pd = static_cast<char *>(h->pump) + d.pump_off * es;
             if (opt.precision == OPO_F64) host_to_state<double>(pd, f[i].pump_in, d.nt, st);
@@ -833,7 +855,8 @@ template <typename R> static int ensure_tables(opo_t *h, double mode)
     for (int o : h->disp_owner) {
         const InstDesc &d = h->inst[o];
         const double dz = mode > 0.0 ? mode : d.length_mm / h->nz;
-        const int blocks = static_cast<int>(std::min<long long>((3LL * d.nt + kThreads - 1) / kThreads, 4096));
+        const int blocks = static_cast<int>(
+            std::min<long long>((static_cast<long long>(d.nf) * d.nt + kThreads - 1) / kThreads, 4096));
         disp_table<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, o, static_cast<Phasor<R> *>(h->d_disp), dz);
     }
     HIP_TRY(hipGetLastError());
@@ -943,7 +966,7 @@ uint64_t opo_state_bytes(int32_t n, const opo_fields_t *fields, int32_t precisio
     if (n <= 0 || !fields) return 0;
     uint64_t s = 0;
     for (int i = 0; i < n; ++i)
-        s += 3ULL * static_cast<uint64_t>(fields[i].nt > 0 ? fields[i].nt : 0);
+        s += static_cast<uint64_t>(nfields(fields[i])) * static_cast<uint64_t>(fields[i].nt > 0 ? fields[i].nt : 0);
     return s * (precision == OPO_F64 ? 16 : 8);
 }
 
@@ -1008,7 +1031,8 @@ int opo_get_fields(opo_t *h, int32_t inst, int32_t field, int32_t domain, double
 {
     int rc = check(h);
     if (rc) return rc;
-    if (inst < 0 || inst >= h->n_inst || field < 0 || field > 2 || !out || domain < 0 || domain > 1)
+    if (inst < 0 || inst >= h->n_inst || field < 0 || field >= h->inst[inst].nf || !out || domain < 0 ||
+        domain > 1)
         return fail(OPO_EINVAL, "bad instance, field, domain or output pointer");
     try {
         if (domain == 1)
@@ -1028,7 +1052,7 @@ int opo_set_fields(opo_t *h, int32_t inst, int32_t field, const double *in)
 {
     int rc = check(h);
     if (rc) return rc;
-    if (inst < 0 || inst >= h->n_inst || field < 0 || field > 2 || !in)
+    if (inst < 0 || inst >= h->n_inst || field < 0 || field >= h->inst[inst].nf || !in)
         return fail(OPO_EINVAL, "bad instance, field or input pointer");
     try {
         const InstDesc &d = h->inst[inst];

@@ -14,10 +14,13 @@
 //   row pass     forward row FFT -> linear propagator / nt -> inverse row FFT
 //
 // The RK4 half-steps (Eqs. 2-4 without the linear operator) are pointwise in
-// time and need the three fields of a sample together, so a column tile holds
-// COLS adjacent columns of all three fields (COLS*8 B = 128 B per row, one
-// cache line); the linear propagator (Eq. 5) is pointwise in frequency and
-// per field, so a row tile holds whole rows of one field. Both kernels keep
+// time and need the fields of a sample together, so a column tile holds COLS
+// adjacent columns of every field (COLS*8 B = 128 B per row, one cache line);
+// the linear propagator (Eq. 5) is pointwise in frequency and per field, so a
+// row tile holds whole rows of one field. An instance couples three waves
+// (pump, signal, idler) or, at degeneracy, two (pump and signal, with the
+// signal equation of the paper's degenerate case and the pump coefficient
+// 2 pi d_eff/(n_p lambda_s) that conserves n_p|A_p|^2 + n_s|A_s|^2). Both kernels keep
 // every sample in registers from load to store (fft_tile.h) and are
 // specialized at compile time for the transform length; the host groups the
 // tiles of a batch by that length and launches each group.
@@ -35,19 +38,20 @@ namespace opo {
 struct InstDesc {
     long long off;        // element offset of the pump field; signal +nt, idler +2nt
     long long pump_off;   // element offset of the input-pump samples, -1 = constant pump
-    long long disp_off;   // offset of the instance's linear-propagator table (3 nt entries)
+    long long disp_off;   // offset of the instance's linear-propagator table (nf nt entries)
     int nt, log2nt;
     int n1, log2n1;       // row length (contiguous)
     int n2, log2n2;       // column length (stride n1)
     int cols;             // columns per column tile
     int rows;             // rows per row tile
     int tile_a0, tiles_a; // first column tile of the instance, and count
-    int tile_b0, tiles_b; // first row tile, and count (3 fields x row blocks)
+    int tile_b0, tiles_b; // first row tile, and count (nf fields x row blocks)
     int tw4_off;          // four-step twiddle tables: 2^tw4_bits low entries, then high
     int tw4_bits;
-    int res_mask, gdd_mask, eom_mask, pad0;
+    int res_mask, gdd_mask, eom_mask;
+    int nf;               // coupled waves: 3 (p, s, i) or 2 (p, s; degenerate)
     double length_mm;
-    double kappa[3];      // 1/mm per V/m
+    double kappa[3];      // 1/mm per V/m; two waves: (kappa_p2, kappa_s, 0)
     double dk_rev;        // dk / (2 pi)  [rev/mm]
     double disp[3][3];    // dispersion phase [rev/mm] = c0 ks + c1 ks^2 + c2 ks^3 per field
     double alpha_half[3]; // alpha_x / 2
@@ -217,6 +221,47 @@ __device__ __forceinline__ void rk4_point(const cplx<R> (&c)[3][3], cplx<R> &ap,
                ai.y + third * (i1.y + two * (i2.y + i3.y) + i4.y));
 }
 
+// The two-wave right-hand side times h/2: (i kappa_p2 A_s^2 e^{-i dk z},
+// i kappa_s A_p A_s^* e^{+i dk z}) with the same stage coefficients.
+template <bool IMAG, typename V>
+__device__ __forceinline__ void cwe2_rhs(const V (&k)[3], V ap, V as, V &fp, V &fs)
+{
+    fp = kmul<IMAG>(k[0], cmul(as, as));
+    fs = kmul<IMAG>(k[1], cmulc(ap, as));
+}
+
+template <typename R, bool IMAG>
+__device__ __forceinline__ void rk4_point2(const cplx<R> (&c)[3][3], cplx<R> &ap, cplx<R> &as)
+{
+    using V = cplx<R>;
+    V p1, s1, p2, s2, p3, s3, p4, s4;
+    cwe2_rhs<IMAG>(c[0], ap, as, p1, s1);
+    cwe2_rhs<IMAG>(c[1], cadd(ap, p1), cadd(as, s1), p2, s2);
+    cwe2_rhs<IMAG>(c[1], cadd(ap, p2), cadd(as, s2), p3, s3);
+    const R two = R(2);
+    cwe2_rhs<IMAG>(c[2], mk<V>(ap.x + two * p3.x, ap.y + two * p3.y), mk<V>(as.x + two * s3.x, as.y + two * s3.y),
+                   p4, s4);
+    const R third = R(1) / R(3);
+    ap = mk<V>(ap.x + third * (p1.x + two * (p2.x + p3.x) + p4.x),
+               ap.y + third * (p1.y + two * (p2.y + p3.y) + p4.y));
+    as = mk<V>(as.x + third * (s1.x + two * (s2.x + s3.x) + s4.x),
+               as.y + third * (s1.y + two * (s2.y + s3.y) + s4.y));
+}
+
+// RK4 half-step of the NF coupled waves at one time point (y2 unused for two).
+template <typename R, int NF>
+__device__ __forceinline__ void rk4_fields(const cplx<R> (&c)[3][3], bool imag, cplx<R> &y0, cplx<R> &y1,
+                                           cplx<R> &y2)
+{
+    if constexpr (NF == 3) {
+        if (imag) rk4_point<R, true>(c, y0, y1, y2);
+        else rk4_point<R, false>(c, y0, y1, y2);
+    } else {
+        if (imag) rk4_point2<R, true>(c, y0, y1);
+        else rk4_point2<R, false>(c, y0, y1);
+    }
+}
+
 // Fixed-order workgroup sum of three doubles; the result is valid in thread 0.
 __device__ __forceinline__ void block_sum3(double v[3], double *scratch /* [3*kThreads/64] */)
 {
@@ -247,9 +292,9 @@ struct ColumnShared {
 };
 
 // ------------------------------------------------------------------------
-// Column pass of one tile: COLS columns j1 = c0 + c of the three fields.
+// Column pass of one tile: COLS columns j1 = c0 + c of the NF fields.
 // Thread (c, t) holds samples j2 (or k2) = t + m*T, m < PF, of column c.
-template <typename R, int LN2>
+template <typename R, int LN2, int NF>
 __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc &d, int tile,
                                             cplx<R> *s, Coupling<R> *cpl, double *red)
 {
@@ -270,7 +315,7 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     if (flags & (A_RK_PREV | A_RK_THIS))
         coupling_tile<R>(d, zb + (a.step - 1) * dz + 0.5 * dz, zb + a.step * dz, dz, cpl);
 
-    V v[3][PF];
+    V v[NF][PF];
     // four-step twiddle W_nt^{j1 k2} of sample m; formed where it is used (before
     // the inverse and after the forward column FFT) rather than held in registers
     const double2 *t4 = a.tw4 + d.tw4_off;
@@ -278,23 +323,26 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
         return twiddle4<R>(t4, d.tw4_bits, (static_cast<unsigned>(j1) * static_cast<unsigned>(t + m * T)) & (nt - 1));
     };
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
+    for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int m = 0; m < PF; ++m)
             v[f][m] = act ? g[static_cast<long long>(f) * nt + static_cast<long long>(n1) * (t + m * T)]
                           : mk<V>(R(0), R(0));
 
-    const int base[3] = {c, COLS * N + c, 2 * COLS * N + c};
+    int base[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+        base[f] = f * COLS * N + c;
     if (flags & A_INV) {
         if constexpr (N > 1) {
 #pragma unroll
             for (int m = 0; m < PF; ++m) {
                 const Phasor<R> w = w4(m);
 #pragma unroll
-                for (int f = 0; f < 3; ++f) v[f][m] = pmul<true>(v[f][m], w);
+                for (int f = 0; f < NF; ++f) v[f][m] = pmul<true>(v[f][m], w);
             }
         }
-        reg_fft<R, N, PF, 3, +1, COLS>(v, s, base, t, a.tw);
+        reg_fft<R, N, PF, NF, +1, COLS>(v, s, base, t, a.tw);
     }
     if (flags & (A_RK_PREV | A_RK_THIS)) __syncthreads();   // couplings visible
 
@@ -304,20 +352,17 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
 #pragma unroll
     for (int m = 0; m < PF; ++m) {
         const long long j = static_cast<long long>(j1) + static_cast<long long>(n1) * (t + m * T);
-        V y0 = v[0][m], y1 = v[1][m], y2 = v[2][m];
-        if (flags & A_RK_PREV) {
-            if (imag) rk4_point<R, true>(cpl->c[0], y0, y1, y2);
-            else rk4_point<R, false>(cpl->c[0], y0, y1, y2);
-        }
+        V y0 = v[0][m], y1 = v[1][m], y2 = v[NF - 1][m];
+        if (flags & A_RK_PREV) rk4_fields<R, NF>(cpl->c[0], imag, y0, y1, y2);
         if ((flags & A_ENERGY) && act) {
             en[0] += static_cast<double>(y0.x) * y0.x + static_cast<double>(y0.y) * y0.y;
             en[1] += static_cast<double>(y1.x) * y1.x + static_cast<double>(y1.y) * y1.y;
-            en[2] += static_cast<double>(y2.x) * y2.x + static_cast<double>(y2.y) * y2.y;
+            if constexpr (NF == 3) en[2] += static_cast<double>(y2.x) * y2.x + static_cast<double>(y2.y) * y2.y;
         }
         if (flags & A_MIRROR) {
             if (d.res_mask & 1) y0 = pmul(y0, make_phasor<R>(d.mirror[0][0], d.mirror[0][1]));
             if (d.res_mask & 2) y1 = pmul(y1, make_phasor<R>(d.mirror[1][0], d.mirror[1][1]));
-            if (d.res_mask & 4) y2 = pmul(y2, make_phasor<R>(d.mirror[2][0], d.mirror[2][1]));
+            if (NF == 3 && (d.res_mask & 4)) y2 = pmul(y2, make_phasor<R>(d.mirror[2][0], d.mirror[2][1]));
         }
         if ((flags & A_EOM) && d.eom_mask) {
             // beta sin(2 pi f t_j), with f t_j reduced modulo one revolution in FP64
@@ -327,20 +372,17 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
             const Phasor<R> e = make_phasor<R>(cs, sn);
             if (d.eom_mask & 1) y0 = pmul(y0, e);
             if (d.eom_mask & 2) y1 = pmul(y1, e);
-            if (d.eom_mask & 4) y2 = pmul(y2, e);
+            if (NF == 3 && (d.eom_mask & 4)) y2 = pmul(y2, e);
         }
         if (flags & A_REFRESH) {
             if (!(d.res_mask & 1)) y0 = (d.pump_off >= 0 && act) ? a.pump[d.pump_off + j] : pcw;
             if (!(d.res_mask & 2)) y1 = mk<V>(R(0), R(0));
-            if (!(d.res_mask & 4)) y2 = mk<V>(R(0), R(0));
+            if (NF == 3 && !(d.res_mask & 4)) y2 = mk<V>(R(0), R(0));
         }
-        if (flags & A_RK_THIS) {
-            if (imag) rk4_point<R, true>(cpl->c[1], y0, y1, y2);
-            else rk4_point<R, false>(cpl->c[1], y0, y1, y2);
-        }
+        if (flags & A_RK_THIS) rk4_fields<R, NF>(cpl->c[1], imag, y0, y1, y2);
         v[0][m] = y0;
         v[1][m] = y1;
-        v[2][m] = y2;
+        if constexpr (NF == 3) v[2][m] = y2;
     }
     if (flags & A_ENERGY) {
         block_sum3(en, red);
@@ -350,19 +392,19 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     }
 
     if (flags & A_FWD) {
-        reg_fft<R, N, PF, 3, -1, COLS>(v, s, base, t, a.tw);
+        reg_fft<R, N, PF, NF, -1, COLS>(v, s, base, t, a.tw);
         if constexpr (N > 1) {
 #pragma unroll
             for (int m = 0; m < PF; ++m) {
                 const Phasor<R> w = w4(m);
 #pragma unroll
-                for (int f = 0; f < 3; ++f) v[f][m] = pmul(v[f][m], w);
+                for (int f = 0; f < NF; ++f) v[f][m] = pmul(v[f][m], w);
             }
         }
     }
     if (act) {
 #pragma unroll
-        for (int f = 0; f < 3; ++f)
+        for (int f = 0; f < NF; ++f)
 #pragma unroll
             for (int m = 0; m < PF; ++m)
                 g[static_cast<long long>(f) * nt + static_cast<long long>(n1) * (t + m * T)] = v[f][m];
@@ -373,7 +415,10 @@ template <typename R, int L, int HI>
 __device__ __forceinline__ void column_dispatch(const StepArgs<R> &a, const InstDesc &d, int tile, cplx<R> *s,
                                                 Coupling<R> *cpl, double *red)
 {
-    if (d.log2n2 == L) column_tile<R, L>(a, d, tile, s, cpl, red);
+    if (d.log2n2 == L) {
+        if (d.nf == 2) column_tile<R, L, 2>(a, d, tile, s, cpl, red);
+        else column_tile<R, L, 3>(a, d, tile, s, cpl, red);
+    }
     else if constexpr (L < HI) column_dispatch<R, L + 1, HI>(a, d, tile, s, cpl, red);
 }
 
@@ -506,7 +551,7 @@ __global__ __launch_bounds__(kThreads, (mixed_min_blocks<R, CR, RR>())) void mix
 }
 
 // ------------------------------------------------------------------------
-// Linear propagator of one z-step (Eq. 5) for the three fields of an instance,
+// Linear propagator of one z-step (Eq. 5) for the nf fields of an instance,
 // H_x(k)/nt = exp{[-alpha_x/2 + i(-db1 w + b2 w^2/2 - b3 w^3/6)] dz}/nt,
 // formed in FP64 (phase reduced modulo one revolution) and stored in the
 // row-pass order: position k2*n1 + k1 holds bin k = k2 + n2*k1.
@@ -515,7 +560,7 @@ __global__ __launch_bounds__(kThreads) void disp_table(const InstDesc *inst, int
                                                        double dz)
 {
     const InstDesc &d = inst[owner];
-    const long long n = 3LL * d.nt;
+    const long long n = static_cast<long long>(d.nf) * d.nt;
     for (long long q = blockIdx.x * static_cast<long long>(kThreads) + threadIdx.x; q < n;
          q += static_cast<long long>(gridDim.x) * kThreads) {
         const int f = static_cast<int>(q / d.nt);

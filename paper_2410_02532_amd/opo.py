@@ -30,7 +30,8 @@ _d2 = ctypes.c_double * 2
 class FieldsT(ctypes.Structure):
     _fields_ = [("nt", ctypes.c_int32), ("t_window_ps", ctypes.c_double), ("lambda_um", _d3),
                 ("n", _d3), ("init", ctypes.POINTER(ctypes.c_double)),
-                ("pump_in", ctypes.POINTER(ctypes.c_double)), ("pump_cw", _d2)]
+                ("pump_in", ctypes.POINTER(ctypes.c_double)), ("pump_cw", _d2),
+                ("n_fields", ctypes.c_int32)]
 
 
 class CrystalT(ctypes.Structure):
@@ -118,10 +119,12 @@ def _structs(instances, nz):
         cr, cav = ins["crystal"], ins["cavity"]
         f = fields[i]
         f.nt = int(cr["nt"])
+        nf = int(cr.get("nf", 3))
+        f.n_fields = nf
         f.t_window_ps = cr["t_window_ps"]
         f.lambda_um = _d3(*cr["lambda_um"])
         f.n = _d3(*cr["n"])
-        init = np.ascontiguousarray(np.asarray(ins["fields"], dtype=np.complex128).reshape(3, f.nt))
+        init = np.ascontiguousarray(np.asarray(ins["fields"], dtype=np.complex128).reshape(nf, f.nt))
         keep.append(init)
         f.init = init.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         pump = np.asarray(ins.get("pump_in", 0.0), dtype=np.complex128)
@@ -158,7 +161,9 @@ def _structs(instances, nz):
 class Opo:
     """A handle over one or several OPO instances on one GPU.
 
-    instances: list of dicts with keys crystal, cavity, fields (3, nt), pump_in.
+    instances: list of dicts with keys crystal, cavity, fields (nf, nt), pump_in; the
+    crystal's ``nf`` (default 3) selects three coupled waves or the two-wave degenerate
+    model.
     The field state lives in a torch uint8 tensor on ``device``; the library
     runs on a torch stream (default priority) created for the handle.
     """
@@ -170,6 +175,7 @@ class Opo:
         self._lib = lib
         self.n, fields, crystals, cavities, keep = _structs(instances, nz)
         self.nts = [int(ins["crystal"]["nt"]) for ins in instances]
+        self.nfs = [int(ins["crystal"].get("nf", 3)) for ins in instances]
         self.precision = OPO_F64 if precision in ("f64", OPO_F64) else OPO_F32
         nbytes = lib.opo_state_bytes(self.n, fields, self.precision)
         self._dev = torch.device("cuda", device)
@@ -199,18 +205,18 @@ class Opo:
         _check(self._lib.opo_sync(self.h))
 
     def get_fields(self, inst=0, domain=0):
-        nt = self.nts[inst]
-        out = np.empty((3, nt), dtype=np.complex128)
-        for x in range(3):
+        nt, nf = self.nts[inst], self.nfs[inst]
+        out = np.empty((nf, nt), dtype=np.complex128)
+        for x in range(nf):
             buf = np.empty(nt, dtype=np.complex128)
             _check(self._lib.opo_get_fields(self.h, inst, x, domain, buf.ctypes.data))
             out[x] = buf
         return out
 
     def set_fields(self, a, inst=0):
-        nt = self.nts[inst]
-        a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128).reshape(3, nt))
-        for x in range(3):
+        nt, nf = self.nts[inst], self.nfs[inst]
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128).reshape(nf, nt))
+        for x in range(nf):
             row = np.ascontiguousarray(a[x])
             _check(self._lib.opo_set_fields(self.h, inst, x, row.ctypes.data))
 

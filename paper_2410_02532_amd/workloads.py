@@ -22,7 +22,11 @@ Recipe (synthetic stand-ins for the paper's workloads, arXiv 2410.02532):
   * pump level in units of the oscillation threshold N = P/P_th, where P_th is
     the plane-wave, dispersionless, undepleted threshold: SRO
     cosh(G L) = 1/sqrt(R_s), DRO cosh(G L) = (1 + sqrt(R_s R_i))/(sqrt(R_s) + sqrt(R_i)),
-    with G^2 = k_s k_i |A_p|^2. This only chooses the input amplitude.
+    with G^2 = k_s k_i |A_p|^2. This only chooses the input amplitude;
+  * degenerate (two-wave) workloads: lambda_p = 0.532 um, lambda_s = 1.064 um
+    (the paper's degenerate examples), other crystal values as above; the
+    in-phase signal quadrature gains e^{G L} per pass with G = k_s |A_p|, so
+    the threshold is sqrt(R_s) e^{G L} = 1 (N = P/P_th as above).
 """
 import math
 
@@ -34,6 +38,8 @@ C0 = 299792458.0
 LAMBDA_P_UM = 1.064
 LAMBDA_S_UM = 1.6
 LAMBDA_I_UM = 1.0 / (1.0 / LAMBDA_P_UM - 1.0 / LAMBDA_S_UM)
+LAMBDA_P_DEG_UM = 0.532
+LAMBDA_S_DEG_UM = 1.064
 
 T_WINDOW_PS = 100.0
 LENGTH_MM = 5.0
@@ -91,6 +97,20 @@ def threshold_amplitude(cr, refl_s, refl_i=None):
     return gl / (cr["length_mm"] * math.sqrt(coupling_product(cr)))
 
 
+def crystal2(nt, **kw):
+    """Two-wave (degenerate) crystal dict: pump 0.532 um, signal 1.064 um."""
+    kw.setdefault("lambdas", (LAMBDA_P_DEG_UM, LAMBDA_S_DEG_UM, LAMBDA_S_DEG_UM))
+    cr = crystal(nt, **kw)
+    cr["nf"] = 2
+    return cr
+
+
+def threshold_amplitude_degenerate(cr, refl_s):
+    """Pump amplitude at the plane-wave threshold of the degenerate oscillator."""
+    k_s = 2.0 * math.pi * cr["deff_pm_per_v"] / (cr["n"][1] * cr["lambda_um"][1]) * 1e-9
+    return -0.5 * math.log(refl_s) / (cr["length_mm"] * k_s)
+
+
 def noise(nt, amplitude, seed):
     """Complex Gaussian noise amplitude*(g1 + i g2)/sqrt(2) from PCG64(seed)."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -123,7 +143,7 @@ def initial_fields(nt, pump, seed):
 def config(name, **over):
     """Workload dict for one named configuration.
 
-    Keys: crystal, cavity, nz, n_rt, fields (3, nt) complex128, pump_in (nt,),
+    Keys: crystal, cavity, nz, n_rt, fields (nf, nt) complex128, pump_in (nt,),
     precision ('f32' or 'f64'), instances (list of such dicts for batches).
     """
     if name == "single_pass":          # one pass, no cavity, Nt = 2^10, complex128
@@ -168,6 +188,35 @@ def config(name, **over):
                              cavity=cavity(refl=(0.0, refls[b], 0.0), delta=(0.0, deltas[b], 0.0)),
                              fields=initial_fields(nt, ap0, 1000 + b),
                              pump_in=np.full(nt, ap0 + 0j)))
+        return dict(name=name, instances=inst, nz=over.get("nz", 100),
+                    n_rt=over.get("n_rt", 500), precision="f32")
+    if name == "degenerate_cw":        # two-wave degenerate CW oscillator, Nt = 2^14
+        nt = over.get("nt", 1 << 14)
+        level = over.get("level", 3.0)
+        refl = over.get("refl", 0.98)
+        cr = crystal2(nt)
+        ap0 = math.sqrt(level) * threshold_amplitude_degenerate(cr, refl)
+        f = initial_fields(nt, ap0, over.get("seed", 1000))
+        return dict(name=name, crystal=cr, cavity=cavity(refl=(0.0, refl, 0.0)),
+                    nz=over.get("nz", 100), n_rt=over.get("n_rt", 2000), fields=f[:2].copy(),
+                    pump_in=np.full(nt, ap0 + 0j), precision=over.get("precision", "f32"))
+    if name == "degenerate_sweep":     # 256 uneven-Nt two-wave degenerate oscillators
+        count = over.get("count", 256)
+        rng = np.random.Generator(np.random.PCG64(4))
+        sizes = 1 << rng.integers(over.get("min_log2", 12), over.get("max_log2", 16) + 1,
+                                  size=count)
+        levels = rng.uniform(1.0, 6.0, size=count)
+        deltas = rng.uniform(-0.5, 0.5, size=count)
+        refls = rng.uniform(0.90, 0.99, size=count)
+        inst = []
+        for b in range(count):
+            nt = int(sizes[b])
+            cr = crystal2(nt)
+            ap0 = math.sqrt(levels[b]) * threshold_amplitude_degenerate(cr, refls[b])
+            f = initial_fields(nt, ap0, 2000 + b)
+            inst.append(dict(crystal=cr,
+                             cavity=cavity(refl=(0.0, refls[b], 0.0), delta=(0.0, deltas[b], 0.0)),
+                             fields=f[:2].copy(), pump_in=np.full(nt, ap0 + 0j)))
         return dict(name=name, instances=inst, nz=over.get("nz", 100),
                     n_rt=over.get("n_rt", 500), precision="f32")
     if name == "dro_large":            # DRO, Nt = 2^20, GDD +-2000 fs^2, EOM 1 rad at 1/T

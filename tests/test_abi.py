@@ -54,6 +54,20 @@ def test_state_bytes():
     assert lib.opo_state_bytes(1, f, 0) == 3 * 256 * 8
     assert lib.opo_state_bytes(1, f, 1) == 3 * 256 * 16
     assert lib.opo_state_bytes(0, f, 0) == 0
+    f[0].n_fields = 2                       # two waves: pump and degenerate signal
+    assert lib.opo_state_bytes(1, f, 0) == 2 * 256 * 8
+    assert lib.opo_state_bytes(1, f, 1) == 2 * 256 * 16
+
+
+def test_two_wave_structs_from_the_binding():
+    cr = W.crystal2(128)
+    f = W.initial_fields(128, 1e6, 1)[:2]
+    ins = dict(crystal=cr, cavity=W.cavity(), fields=f, pump_in=np.full(128, 1e6 + 0j))
+    n, fs, c, k, keep = B._structs([ins], 10)
+    assert fs[0].n_fields == 2
+    assert B.load().opo_state_bytes(1, fs, 0) == 2 * 128 * 8
+    with pytest.raises(ValueError):
+        B._structs([dict(ins, fields=W.initial_fields(128, 1e6, 1))], 10)   # (3, nt) for nf = 2
 
 
 @pytest.mark.parametrize("mutate, what", [
@@ -66,6 +80,8 @@ def test_state_bytes():
     (lambda f, c, k: k[0].refl.__setitem__(1, 1.5), "reflectivit"),
     (lambda f, c, k: c[0].b2_fs2_per_mm.__setitem__(0, float("inf")), "finite"),
     (lambda f, c, k: setattr(c[0], "deff_pm_per_v", 1e6), "step too large"),
+    (lambda f, c, k: setattr(f[0], "n_fields", 4), "n_fields"),
+    (lambda f, c, k: setattr(f[0], "n_fields", 1), "n_fields"),
 ])
 def test_init_rejects_bad_arguments(mutate, what):
     n, f, c, k, keep = _one()
