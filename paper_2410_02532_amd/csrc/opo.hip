@@ -68,6 +68,7 @@ struct Group {
     int tile0;    // first tile
     int count;    // tiles
     int half;     // half of the batch (mixed schedule), 0 otherwise
+    int nf;       // coupled waves of the group's instances (column groups)
 };
 
 // Index of the size range (kColRanges / kRowRanges) that contains ln.
@@ -78,14 +79,19 @@ template <size_t K> static int range_of(const int (&ranges)[K][2], int ln)
     return -1;
 }
 
-template <typename R> static const void *column_fn(int range)
+template <typename R, int NF> static const void *column_fn_nf(int range)
 {
     switch (range) {
-    case 0: return reinterpret_cast<const void *>(&column_pass<R, kColRanges[0][0], kColRanges[0][1]>);
-    case 1: return reinterpret_cast<const void *>(&column_pass<R, kColRanges[1][0], kColRanges[1][1]>);
-    case 2: return reinterpret_cast<const void *>(&column_pass<R, kColRanges[2][0], kColRanges[2][1]>);
+    case 0: return reinterpret_cast<const void *>(&column_pass<R, kColRanges[0][0], kColRanges[0][1], NF>);
+    case 1: return reinterpret_cast<const void *>(&column_pass<R, kColRanges[1][0], kColRanges[1][1], NF>);
+    case 2: return reinterpret_cast<const void *>(&column_pass<R, kColRanges[2][0], kColRanges[2][1], NF>);
     default: return nullptr;
     }
+}
+
+template <typename R> static const void *column_fn(int range, int nf)
+{
+    return nf == 2 ? column_fn_nf<R, 2>(range) : column_fn_nf<R, 3>(range);
 }
 
 template <typename R> static const void *row_fn(int range)
@@ -103,25 +109,34 @@ template <typename R> static const void *row_fn(int range)
 
 // Mixed column/row kernels for the (column range, row range) pairs that the
 // four-step split produces.
-template <typename R> static const void *mixed_fn(int cr, int rr)
+template <typename R, int NF> static const void *mixed_fn_nf(int cr, int rr)
 {
     const int key = cr * 3 + rr;
     switch (key) {
-    case 0: return reinterpret_cast<const void *>(&mixed_pass<R, 0, 0>);
-    case 1: return reinterpret_cast<const void *>(&mixed_pass<R, 0, 1>);
+    case 0: return reinterpret_cast<const void *>(&mixed_pass<R, 0, 0, NF>);
+    case 1: return reinterpret_cast<const void *>(&mixed_pass<R, 0, 1, NF>);
     case 2:
-        if constexpr (kMaxLog2N1<R> >= kRowRanges[2][0]) return reinterpret_cast<const void *>(&mixed_pass<R, 0, 2>);
+        if constexpr (kMaxLog2N1<R> >= kRowRanges[2][0])
+            return reinterpret_cast<const void *>(&mixed_pass<R, 0, 2, NF>);
         return nullptr;
-    case 4: return reinterpret_cast<const void *>(&mixed_pass<R, 1, 1>);
+    case 4: return reinterpret_cast<const void *>(&mixed_pass<R, 1, 1, NF>);
     case 5:
-        if constexpr (kMaxLog2N1<R> >= kRowRanges[2][0]) return reinterpret_cast<const void *>(&mixed_pass<R, 1, 2>);
+        if constexpr (kMaxLog2N1<R> >= kRowRanges[2][0])
+            return reinterpret_cast<const void *>(&mixed_pass<R, 1, 2, NF>);
         return nullptr;
-    case 7: return reinterpret_cast<const void *>(&mixed_pass<R, 2, 1>);
+    case 7: return reinterpret_cast<const void *>(&mixed_pass<R, 2, 1, NF>);
     case 8:
-        if constexpr (kMaxLog2N1<R> >= kRowRanges[2][0]) return reinterpret_cast<const void *>(&mixed_pass<R, 2, 2>);
+        if constexpr (kMaxLog2N1<R> >= kRowRanges[2][0])
+            return reinterpret_cast<const void *>(&mixed_pass<R, 2, 2, NF>);
         return nullptr;
     default: return nullptr;
     }
+}
+
+// Mixed kernel for column range cr of nf-wave instances and row range rr.
+template <typename R> static const void *mixed_fn(int cr, int rr, int nf)
+{
+    return nf == 2 ? mixed_fn_nf<R, 2>(cr, rr) : mixed_fn_nf<R, 3>(cr, rr);
 }
 
 } // namespace opo
@@ -407,7 +422,7 @@ template <typename R> static void launch_a(opo_t *h, StepArgs<R> a, int flags, i
         a.tile0 = g.tile0;
         a.tile_count = g.count;
         void *args[] = {&a};
-        (void)hipLaunchKernel(column_fn<R>(g.ln), dim3(g.count), dim3(kThreads), args, h->lds_a, h->stream);
+        (void)hipLaunchKernel(column_fn<R>(g.ln, g.nf), dim3(g.count), dim3(kThreads), args, h->lds_a, h->stream);
     }
     prof_end(h);
 }
@@ -444,7 +459,7 @@ template <typename R> static void launch_mixed(opo_t *h, StepArgs<R> a, int ch, 
     ar.tile_count = gr.count;
     void *args[] = {&ac, &ar};
     prof_begin(h, OPO_K_MIXED);
-    (void)hipLaunchKernel(mixed_fn<R>(gc.ln, gr.ln), dim3(h->map_len[ch]), dim3(kThreads), args,
+    (void)hipLaunchKernel(mixed_fn<R>(gc.ln, gr.ln, gc.nf), dim3(h->map_len[ch]), dim3(kThreads), args,
                           std::max(h->lds_a, h->lds_b), h->stream);
     prof_end(h);
 }
@@ -496,8 +511,8 @@ template <typename R> static void enqueue_roundtrip(opo_t *h)
 template <typename R> static int setup_kernels(opo_t *h)
 {
     for (const Group &g : h->groups_a) {
-        if (!column_fn<R>(g.ln)) return fail(OPO_EINVAL, "internal: no column kernel for this size");
-        HIP_TRY(hipFuncSetAttribute(column_fn<R>(g.ln), hipFuncAttributeMaxDynamicSharedMemorySize,
+        if (!column_fn<R>(g.ln, g.nf)) return fail(OPO_EINVAL, "internal: no column kernel for this size");
+        HIP_TRY(hipFuncSetAttribute(column_fn<R>(g.ln, g.nf), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     static_cast<int>(h->lds_a)));
     }
     for (const Group &g : h->groups_b) {
@@ -506,10 +521,12 @@ template <typename R> static int setup_kernels(opo_t *h)
                                     static_cast<int>(h->lds_b)));
     }
     if (h->mixed)
-        for (int hf = 0; hf < 2; ++hf)
-            HIP_TRY(hipFuncSetAttribute(mixed_fn<R>(h->groups_a[1 - hf].ln, h->groups_b[hf].ln),
+        for (int hf = 0; hf < 2; ++hf) {
+            const Group &gc = h->groups_a[1 - hf];
+            HIP_TRY(hipFuncSetAttribute(mixed_fn<R>(gc.ln, h->groups_b[hf].ln, gc.nf),
                                         hipFuncAttributeMaxDynamicSharedMemorySize,
                                         static_cast<int>(std::max(h->lds_a, h->lds_b))));
+        }
     return OPO_OK;
 }
 
@@ -684,17 +701,18 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     constexpr int ncr = sizeof(kColRanges) / sizeof(kColRanges[0]);
     constexpr int nrr = sizeof(kRowRanges) / sizeof(kRowRanges[0]);
     for (int hf = 0; hf < 2; ++hf)
-        for (int g = 0; g < ncr; ++g) {
-            const int first = h->tiles_a;
-            for (int i = 0; i < n; ++i) {
-                InstDesc &d = h->inst[i];
-                if (half[i] != hf || range_of(kColRanges, d.log2n2) != g) continue;
-                d.tile_a0 = h->tiles_a;
-                h->tiles_a += d.tiles_a;
-                tile_a_inst.insert(tile_a_inst.end(), d.tiles_a, i);
+        for (int nf = 3; nf >= 2; --nf)
+            for (int g = 0; g < ncr; ++g) {
+                const int first = h->tiles_a;
+                for (int i = 0; i < n; ++i) {
+                    InstDesc &d = h->inst[i];
+                    if (half[i] != hf || d.nf != nf || range_of(kColRanges, d.log2n2) != g) continue;
+                    d.tile_a0 = h->tiles_a;
+                    h->tiles_a += d.tiles_a;
+                    tile_a_inst.insert(tile_a_inst.end(), d.tiles_a, i);
+                }
+                if (h->tiles_a > first) h->groups_a.push_back({g, first, h->tiles_a - first, hf, nf});
             }
-            if (h->tiles_a > first) h->groups_a.push_back({g, first, h->tiles_a - first, hf});
-        }
     for (int hf = 0; hf < 2; ++hf)
         for (int g = 0; g < nrr; ++g) {
             const int first = h->tiles_b;
@@ -705,7 +723,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
                 h->tiles_b += d.tiles_b;
                 tile_b_inst.insert(tile_b_inst.end(), d.tiles_b, i);
             }
-            if (h->tiles_b > first) h->groups_b.push_back({g, first, h->tiles_b - first, hf});
+            if (h->tiles_b > first) h->groups_b.push_back({g, first, h->tiles_b - first, hf, 0});
         }
     if (static_cast<int>(tile_a_inst.size()) != h->tiles_a || static_cast<int>(tile_b_inst.size()) != h->tiles_b)
         return bail(fail(OPO_EINVAL, "internal: a transform length has no kernel"));
@@ -715,8 +733,9 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         const bool f64 = opt.precision == OPO_F64;
         h->mixed = true;
         for (int hf = 0; hf < 2; ++hf) {
-            const void *fn = f64 ? mixed_fn<double>(h->groups_a[1 - hf].ln, h->groups_b[hf].ln)
-                                 : mixed_fn<float>(h->groups_a[1 - hf].ln, h->groups_b[hf].ln);
+            const Group &gc = h->groups_a[1 - hf];
+            const void *fn = f64 ? mixed_fn<double>(gc.ln, h->groups_b[hf].ln, gc.nf)
+                                 : mixed_fn<float>(gc.ln, h->groups_b[hf].ln, gc.nf);
             h->mixed = h->mixed && fn != nullptr;
         }
     }

@@ -411,27 +411,24 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     }
 }
 
-template <typename R, int L, int HI>
+template <typename R, int L, int HI, int NF>
 __device__ __forceinline__ void column_dispatch(const StepArgs<R> &a, const InstDesc &d, int tile, cplx<R> *s,
                                                 Coupling<R> *cpl, double *red)
 {
-    if (d.log2n2 == L) {
-        if (d.nf == 2) column_tile<R, L, 2>(a, d, tile, s, cpl, red);
-        else column_tile<R, L, 3>(a, d, tile, s, cpl, red);
-    }
-    else if constexpr (L < HI) column_dispatch<R, L + 1, HI>(a, d, tile, s, cpl, red);
+    if (d.log2n2 == L) column_tile<R, L, NF>(a, d, tile, s, cpl, red);
+    else if constexpr (L < HI) column_dispatch<R, L + 1, HI, NF>(a, d, tile, s, cpl, red);
 }
 
-// Column pass over the tiles of instances whose log2 n2 lies in [LO, HI].
-template <typename R, int LO, int HI>
+// Column pass over the tiles of NF-wave instances whose log2 n2 lies in [LO, HI].
+template <typename R, int LO, int HI, int NF>
 __global__ __launch_bounds__(kThreads) void column_pass(StepArgs<R> a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ Coupling<R> cpl;
     __shared__ double red[3 * kThreads / 64];
     const int tile = a.tile0 + blockIdx.x;
-    column_dispatch<R, LO, HI>(a, a.inst[a.tile_inst[tile]], tile, reinterpret_cast<cplx<R> *>(lds_raw), &cpl,
-                               red);
+    column_dispatch<R, LO, HI, NF>(a, a.inst[a.tile_inst[tile]], tile, reinterpret_cast<cplx<R> *>(lds_raw),
+                                   &cpl, red);
 }
 
 // ------------------------------------------------------------------------
@@ -526,13 +523,18 @@ constexpr int kRowRanges[][2] = {{0, 5}, {6, 11}, {12, 12}};
 // table instead of all of it.
 // Workgroups per CU the mixed kernel is compiled for: four (at most 128
 // VGPRs) for FP32 columns of up to 64 points, which fit that without spills,
-// else whatever the registers allow.
-template <typename R, int CR, int RR> constexpr int mixed_min_blocks() { return sizeof(R) == 4 && CR == 0 && RR <= 1 ? 4 : 1; }
+// else whatever the registers allow. (Five for two waves spills a few
+// registers and runs no faster.)
+template <typename R, int CR, int RR> constexpr int mixed_min_blocks()
+{
+    return sizeof(R) == 4 && CR == 0 && RR <= 1 ? 4 : 1;
+}
 
 constexpr int kNoTile = -2147483647 - 1;
 
-template <typename R, int CR, int RR>
-__global__ __launch_bounds__(kThreads, (mixed_min_blocks<R, CR, RR>())) void mixed_pass(StepArgs<R> ac, StepArgs<R> ar)
+template <typename R, int CR, int RR, int NF>
+__global__ __launch_bounds__(kThreads, (mixed_min_blocks<R, CR, RR>())) void mixed_pass(StepArgs<R> ac,
+                                                                                        StepArgs<R> ar)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ Coupling<R> cpl;
@@ -542,7 +544,7 @@ __global__ __launch_bounds__(kThreads, (mixed_min_blocks<R, CR, RR>())) void mix
     const int code = ac.block_map[blockIdx.x];
     if (code == kNoTile) return;
     if (code >= 0) {
-        column_dispatch<R, kColRanges[CR][0], kColRanges[CR][1]>(ac, ac.inst[ac.tile_inst[code]], code, s, &cpl,
+        column_dispatch<R, kColRanges[CR][0], kColRanges[CR][1], NF>(ac, ac.inst[ac.tile_inst[code]], code, s, &cpl,
                                                                  red);
     } else {
         const int tile = -1 - code;
