@@ -19,6 +19,9 @@
  *   Sec. 2.3   intracavity GDD and EOM                      -> ora_gdd, ora_eom
  *   Sec. 4.1   main loop: pump read, pass, GDD, phase, EOM  -> ora_roundtrips
  *   Sec. 2.4   degenerate signal equation (two waves)        -> cwe2_rhs
+ *   Sec. 4.1   nanosecond regime: long pump read slice by slice,
+ *              per-round-trip output record (ReadPump,
+ *              SaveRoundTrip)                                -> ora_roundtrips_rec
  *
  * Readings of passages the paper leaves open (each one is also recorded in
  * the design notes):
@@ -38,6 +41,11 @@
  *     pump and non-resonant signal/idler start at zero; after the pass the
  *     energies sum_j |A_x(t_j)|^2 are recorded, then GDD, then
  *     sqrt(R_x) e^{i delta_x} on resonant fields, then the EOM phase.
+ *   - Nanosecond regime: the input pump is a long record of n_slices
+ *     consecutive windows of nt samples; round trip m reads window m into a
+ *     non-resonant pump, and a zero pump once the record is exhausted. The
+ *     per-round-trip output is each field as it leaves the crystal (after the
+ *     pass, before GDD and the mirror), stored as window m of the output.
  *   - Two coupled waves (degenerate operation, signal = idler; nf = 2): the
  *     paper gives the signal equation dA_s/dz = i kappa_s A_p A_s^* (with
  *     e^{+i dk z}) and leaves the pump equation unprinted. We take
@@ -324,25 +332,33 @@ void ora_eom(cplx *field, int n, double t_window_ps, double beta, double fpm_thz
 
 /* ----------------------------------------------------- round trips -- */
 
-/* n_rt cavity round trips (Sec. 4.1 main loop with Eq. 6). energy[m*3+x]
- * receives sum_j |A_x(t_j)|^2 after the crystal pass of round trip m (0 for
- * x >= nf).
- * pump_in: nt input-pump samples read into a non-resonant pump at the
- * start of every round trip. */
-void ora_roundtrips(const ora_crystal *c, const ora_cavity *cav, cplx *a,
-                    const cplx *pump_in, int nz, int n_rt, double *energy)
+/* Round trips with a long input pump and an output record (nanosecond
+ * regime). pump_in holds n_slices windows of nt samples; round trip m reads
+ * window m (m < n_slices) into a non-resonant pump, else a zero pump.
+ * record, if not NULL, receives window m of every field as it leaves the
+ * crystal: record[(m*nf + x)*nt + j]. energy[m*3+x] as ora_roundtrips. */
+static void roundtrips(const ora_crystal *c, const ora_cavity *cav, cplx *a,
+                       const cplx *pump_in, int n_slices, int same_pump, int nz, int n_rt,
+                       double *energy, cplx *record)
 {
     int n = c->nt;
     double dz = c->length_mm / (double)nz;
     for (int m = 0; m < n_rt; m++) {
-        if (!cav->resonant[0])
-            memcpy(a, pump_in, sizeof(cplx) * (size_t)n);
+        if (!cav->resonant[0]) {
+            int w = same_pump ? 0 : m;
+            if (w < n_slices)
+                memcpy(a, pump_in + (size_t)w * n, sizeof(cplx) * (size_t)n);
+            else
+                memset(a, 0, sizeof(cplx) * (size_t)n);
+        }
         for (int x = 1; x < c->nf; x++)
             if (!cav->resonant[x])
                 memset(a + (size_t)x * n, 0, sizeof(cplx) * (size_t)n);
 
         ora_pass(c, a, nz, dz, 0.0);
 
+        if (record)
+            memcpy(record + (size_t)m * c->nf * n, a, sizeof(cplx) * (size_t)c->nf * n);
         for (int x = 0; x < 3; x++) {
             double e = 0.0;
             if (x >= c->nf) {
@@ -368,4 +384,20 @@ void ora_roundtrips(const ora_crystal *c, const ora_cavity *cav, cplx *a,
             if (cav->eom_on[x] && cav->eom_beta != 0.0)
                 ora_eom(a + (size_t)x * n, n, c->t_window_ps, cav->eom_beta, cav->eom_fpm_thz);
     }
+}
+
+void ora_roundtrips_rec(const ora_crystal *c, const ora_cavity *cav, cplx *a,
+                        const cplx *pump_in, int n_slices, int nz, int n_rt,
+                        double *energy, cplx *record)
+{
+    roundtrips(c, cav, a, pump_in, n_slices, 0, nz, n_rt, energy, record);
+}
+
+/* n_rt cavity round trips (Sec. 4.1 main loop with Eq. 6) with the same
+ * input pump every round trip. energy[m*3+x] receives sum_j |A_x(t_j)|^2
+ * after the crystal pass of round trip m (0 for x >= nf). */
+void ora_roundtrips(const ora_crystal *c, const ora_cavity *cav, cplx *a,
+                    const cplx *pump_in, int nz, int n_rt, double *energy)
+{
+    roundtrips(c, cav, a, pump_in, 1, 1, nz, n_rt, energy, NULL);
 }

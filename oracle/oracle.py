@@ -109,6 +109,8 @@ def _load():
         lib.ora_eom.argtypes = [P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
         lib.ora_roundtrips.argtypes = [ctypes.POINTER(Crystal), ctypes.POINTER(Cavity), P, P,
                                        ctypes.c_int, ctypes.c_int, P]
+        lib.ora_roundtrips_rec.argtypes = [ctypes.POINTER(Crystal), ctypes.POINTER(Cavity), P, P,
+                                           ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
         _lib = lib
     return _lib
 
@@ -217,3 +219,22 @@ def roundtrips(crystal, cavity, a, pump_in, nz, n_rt):
                            ctypes.byref(Cavity.from_dict(cavity)), _ptr(a), _ptr(p),
                            int(nz), int(n_rt), _ptr(e))
     return a, e
+
+
+def roundtrips_record(crystal, cavity, a, pump_long, nz, n_rt, record=True):
+    """Nanosecond regime: round trip m reads window m of pump_long (n_slices x nt samples,
+    a zero pump after the last window) into a non-resonant pump. Returns (fields,
+    energies[n_rt, 3], record[n_rt, nf, nt] of the fields leaving the crystal, or None)."""
+    nt = crystal["nt"]
+    nf = _nf(crystal)
+    a = _fields(a, crystal)
+    p = _cplx(np.asarray(pump_long, dtype=np.complex128).reshape(-1))
+    if p.size % nt or p.size == 0:
+        raise ValueError("pump_long must hold whole windows of nt samples")
+    e = np.zeros((int(n_rt), 3))
+    rec = np.zeros((int(n_rt), nf, nt), dtype=np.complex128) if record else None
+    _load().ora_roundtrips_rec(ctypes.byref(Crystal.from_dict(crystal)),
+                               ctypes.byref(Cavity.from_dict(cavity)), _ptr(a), _ptr(p),
+                               p.size // nt, int(nz), int(n_rt), _ptr(e),
+                               _ptr(rec) if record else None)
+    return a, e, rec

@@ -26,7 +26,12 @@ Recipe (synthetic stand-ins for the paper's workloads, arXiv 2410.02532):
   * degenerate (two-wave) workloads: lambda_p = 0.532 um, lambda_s = 1.064 um
     (the paper's degenerate examples), other crystal values as above; the
     in-phase signal quadrature gains e^{G L} per pass with G = k_s |A_p|, so
-    the threshold is sqrt(R_s) e^{G L} = 1 (N = P/P_th as above).
+    the threshold is sqrt(R_s) e^{G L} = 1 (N = P/P_th as above);
+  * nanosecond regime: a 10 ns (intensity FWHM) Gaussian pump spread over
+    consecutive round-trip windows of T = 100 ps (one window per round trip),
+    centred in the record; the paper's peak powers 75, 100 and 250 W keep
+    their ratios as peak levels of 3, 4 and 10 times the CW threshold at
+    R_s = 0.5 (the beam size that would fix the absolute scale is not printed).
 """
 import math
 
@@ -109,6 +114,15 @@ def threshold_amplitude_degenerate(cr, refl_s):
     """Pump amplitude at the plane-wave threshold of the degenerate oscillator."""
     k_s = 2.0 * math.pi * cr["deff_pm_per_v"] / (cr["n"][1] * cr["lambda_um"][1]) * 1e-9
     return -0.5 * math.log(refl_s) / (cr["length_mm"] * k_s)
+
+
+def long_pulse(nt, n_windows, peak, fwhm_ps, t_window_ps=T_WINDOW_PS):
+    """A Gaussian pump e^{-t^2/(2 T0^2)} (intensity FWHM fwhm_ps) sampled over n_windows
+    consecutive windows of nt points, centred in the record; shape (n_windows, nt)."""
+    t0 = fwhm_ps / (2.0 * math.sqrt(math.log(2.0)))
+    centre = 0.5 * n_windows * t_window_ps
+    t = (np.arange(n_windows)[:, None] + 0.5) * t_window_ps + time_grid(nt, t_window_ps)[None, :]
+    return peak * np.exp(-(t - centre) ** 2 / (2.0 * t0 * t0)) + 0j
 
 
 def noise(nt, amplitude, seed):
@@ -219,6 +233,22 @@ def config(name, **over):
                              fields=f[:2].copy(), pump_in=np.full(nt, ap0 + 0j)))
         return dict(name=name, instances=inst, nz=over.get("nz", 100),
                     n_rt=over.get("n_rt", 500), precision="f32")
+    if name == "ns_pulsed":            # degenerate OPO pumped by 10 ns pulses, window per RT
+        nt = over.get("nt", 1 << 12)
+        windows = over.get("windows", 400)
+        refl = over.get("refl", 0.5)
+        levels = over.get("levels", (3.0, 4.0, 10.0))
+        inst = []
+        for b, level in enumerate(levels):
+            cr = crystal2(nt)
+            peak = math.sqrt(level) * threshold_amplitude_degenerate(cr, refl)
+            pump = long_pulse(nt, windows, peak, over.get("fwhm_ps", 10000.0))
+            f = initial_fields(nt, peak, 3000 + b)
+            f[0] = pump[0]
+            inst.append(dict(crystal=cr, cavity=cavity(refl=(0.0, refl, 0.0)),
+                             fields=f[:2].copy(), pump_in=pump))
+        return dict(name=name, instances=inst, nz=over.get("nz", 100),
+                    n_rt=over.get("n_rt", windows), precision="f32")
     if name == "dro_large":            # DRO, Nt = 2^20, GDD +-2000 fs^2, EOM 1 rad at 1/T
         nt = over.get("nt", 1 << 20)
         count = over.get("count", 16)
