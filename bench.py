@@ -231,6 +231,15 @@ def main():
         var["f32_degenerate_sweep"] = {"value": pt_steps_per_rt(ws) * n / d, "round_trips": n,
                                        "ms_per_step": d * 1e3 / n, "instances": len(ws["instances"]),
                                        "fields": 2}
+        # nanosecond regime: 10 ns pulses read one window per round trip, with the
+        # per-round-trip record of the fields leaving the crystal
+        ws = W.config("ns_pulsed")
+        n = ws["n_rt"]
+        with B.from_workload(ws, record_rt=n) as h:
+            d, _ = timed_roundtrips(h, n)
+        var["f32_ns_pulsed"] = {"value": pt_steps_per_rt(ws) * n / d, "round_trips": n,
+                                "ms_per_step": d * 1e3 / n, "instances": len(ws["instances"]),
+                                "nt": ws["instances"][0]["crystal"]["nt"], "record": True}
         line["variants"] = var
         print("variants: %s" % json.dumps(var), file=sys.stderr, flush=True)
 

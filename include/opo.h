@@ -67,11 +67,18 @@ typedef struct {
     const double *init;     /* n_fields*nt complex128 initial fields p, s(, i)
                                (time domain), host memory, copied; NULL = zero    */
     const double *pump_in;  /* nt complex128 input pump read into a non-resonant
-                               pump at the start of every round trip; NULL = the
+                               pump at the start of every round trip (or
+                               pump_windows windows of nt, see below); NULL = the
                                constant pump_cw below                             */
     double pump_cw[2];      /* constant input pump (re, im) when pump_in is NULL  */
     int32_t n_fields;       /* coupled waves: 3 (or 0) = pump, signal, idler;
                                2 = pump and degenerate signal                     */
+    int32_t pump_windows;   /* nanosecond regime (Sec. 4.1 pump read): pump_in
+                               holds pump_windows consecutive windows of nt
+                               samples and round trip m (counted from opo_init)
+                               reads window m, then a zero pump once m >=
+                               pump_windows; 0 or 1 = the same nt samples every
+                               round trip                                         */
 } opo_fields_t;
 
 /* Crystal: length, z-grid and the coefficients of Eqs. 2-5. */
@@ -123,6 +130,12 @@ typedef struct {
                                per-kernel device time (plain launches instead of
                                the graph, one stream synchronization per round
                                trip); read with opo_kernel_times                  */
+    int32_t record_rt;      /* > 0: keep on the device, for each of the first
+                               record_rt round trips (counted from opo_init),
+                               every field as it leaves the crystal (after the
+                               pass, before GDD and the mirror; Sec. 4.1 round-
+                               trip save), read with opo_get_record. Costs
+                               record_rt * opo_state_bytes() of device memory     */
 } opo_options_t;
 
 /* Device bytes of field state for n instances (n_fields * nt complex values
@@ -174,6 +187,12 @@ int opo_set_fields(opo_t *h, int32_t inst, int32_t field, const double *in);
  * so far. */
 int opo_get_energy_history(opo_t *h, int32_t inst, double *out, int32_t capacity,
                            int32_t *rows);
+
+/* Field `field` of instance `inst` as it left the crystal in round trip rt
+ * (counted from opo_init; rt < record_rt and < the round trips run so far),
+ * nt interleaved complex128 time samples, from the record of the record_rt
+ * option. OPO_EINVAL for a round trip outside the record. */
+int opo_get_record(opo_t *h, int32_t inst, int32_t field, int32_t rt, double *out);
 
 /* Time samples t_j [ps] and angular frequencies w_k [rad/ps] of an instance. */
 int opo_get_grid(opo_t *h, int32_t inst, double *t, double *omega);

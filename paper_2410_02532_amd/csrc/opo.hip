@@ -169,7 +169,9 @@ struct opo_s {
     double disp_mode = -1.0;         // step the tables hold: > 0 explicit dz, 0 = L/nz, < 0 none
     double *d_partial = nullptr;
     double *d_hist = nullptr;
-    int *d_counter = nullptr;
+    int *d_counter = nullptr;        // [0] history slot in the chunk, [1] round trips completed
+    void *d_record = nullptr;        // [record_cap][state] fields leaving the crystal per round trip
+    int record_cap = 0;
     size_t lds_a = 0, lds_b = 0;
     double z = 0.0;
     std::vector<double> hist;        // [rows][n_inst][3]
@@ -244,6 +246,8 @@ static int validate(int n, const opo_fields_t *f, const opo_crystal_t *c, const 
                 return fail(OPO_EINVAL, at + "wavelengths and indices must be finite and > 0");
         if (!std::isfinite(f[i].pump_cw[0]) || !std::isfinite(f[i].pump_cw[1]))
             return fail(OPO_EINVAL, at + "pump_cw must be finite");
+        if (f[i].pump_windows < 0 || (f[i].pump_windows > 1 && !f[i].pump_in))
+            return fail(OPO_EINVAL, at + "pump_windows must be >= 0, and > 1 only with pump_in");
         if (!(c[i].length_mm > 0.0) || !std::isfinite(c[i].length_mm))
             return fail(OPO_EINVAL, at + "length_mm must be finite and > 0");
         if (c[i].nz < 1) return fail(OPO_EINVAL, at + "nz must be >= 1");
@@ -267,7 +271,7 @@ static int validate(int n, const opo_fields_t *f, const opo_crystal_t *c, const 
             for (long long q = 0; q < static_cast<long long>(nf) * nt; ++q)
                 amax = std::max(amax, std::hypot(f[i].init[2 * q], f[i].init[2 * q + 1]));
         if (f[i].pump_in)
-            for (long long q = 0; q < nt; ++q)
+            for (long long q = 0; q < static_cast<long long>(nt) * std::max(1, f[i].pump_windows); ++q)
                 amax = std::max(amax, std::hypot(f[i].pump_in[2 * q], f[i].pump_in[2 * q + 1]));
         if (!std::isfinite(amax)) return fail(OPO_EINVAL, at + "initial fields must be finite");
         double kap[3], kmax = 0.0;
@@ -346,7 +350,7 @@ static void release(opo_t *h)
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->own_state && h->state) (void)hipFree(h->state);
     void *bufs[] = {h->pump, h->d_inst, h->d_tile_a, h->d_tile_b, h->d_tw, h->d_tw4, h->d_disp, h->d_map[0], h->d_map[1],
-                    h->d_partial, h->d_hist, h->d_counter, h->scratch};
+                    h->d_partial, h->d_hist, h->d_counter, h->scratch, h->d_record};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : h->events)
@@ -369,6 +373,10 @@ template <typename R> static StepArgs<R> base_args(opo_t *h, void *state)
     a.tw4 = static_cast<const double2 *>(h->d_tw4);
     a.disp = static_cast<const Phasor<R> *>(h->d_disp);
     a.partial = h->d_partial;
+    a.counter = h->d_counter;
+    a.record = static_cast<cplx<R> *>(h->d_record);
+    a.record_stride = static_cast<long long>(h->state_bytes / h->elem);
+    a.record_cap = h->record_cap;
     a.nz = h->nz;
     return a;
 }
@@ -540,6 +548,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     if (opt.profile) opt.use_graph = -1;
     if (opt.precision != OPO_F32 && opt.precision != OPO_F64)
         return fail(OPO_EINVAL, "precision must be OPO_F32 or OPO_F64");
+    if (opt.record_rt < 0) return fail(OPO_EINVAL, "record_rt must be >= 0");
     int rc = validate(n, f, c, k, opt.precision);
     if (rc) return rc;
 
@@ -598,9 +607,10 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         d.off = off;
         off += static_cast<long long>(d.nf) * d.nt;
         d.pump_off = -1;
+        d.pump_windows = f[i].pump_windows > 1 ? f[i].pump_windows : 1;
         if (f[i].pump_in) {
             d.pump_off = pump_elems;
-            pump_elems += d.nt;
+            pump_elems += static_cast<long long>(d.nt) * d.pump_windows;
         }
         d.tiles_a = (d.n1 + d.cols - 1) / d.cols;
         d.tiles_b = d.nf * ((d.n2 + d.rows - 1) / d.rows);
@@ -786,6 +796,11 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     const size_t es = h->elem;
     if (pump_elems && hipMalloc(&h->pump, pump_elems * es) != hipSuccess)
         return bail(fail(OPO_ENOMEM, "hipMalloc of the input pump failed"));
+    if (opt.record_rt > 0) {
+        if (hipMalloc(&h->d_record, static_cast<size_t>(opt.record_rt) * need) != hipSuccess)
+            return bail(fail(OPO_ENOMEM, "hipMalloc of the round-trip record failed"));
+        h->record_cap = opt.record_rt;
+    }
     if (hipMalloc(reinterpret_cast<void **>(&h->d_inst), n * sizeof(InstDesc)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_tile_a), h->tiles_a * sizeof(int)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_tile_b), h->tiles_b * sizeof(int)) != hipSuccess ||
@@ -795,7 +810,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         hipMalloc(reinterpret_cast<void **>(&h->d_partial), h->tiles_a * 3 * sizeof(double)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_hist),
                   static_cast<size_t>(kHistChunk) * n * 3 * sizeof(double)) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void **>(&h->d_counter), sizeof(int)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&h->d_counter), 2 * sizeof(int)) != hipSuccess ||
         (h->mixed && (hipMalloc(reinterpret_cast<void **>(&h->d_map[0]), maps[0].size() * sizeof(int)) != hipSuccess ||
                       hipMalloc(reinterpret_cast<void **>(&h->d_map[1]), maps[1].size() * sizeof(int)) != hipSuccess)))
         return bail(fail(OPO_ENOMEM, "hipMalloc of the tables failed"));
@@ -842,10 +857,12 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         else host_to_state<float>(dst, src, count, st);
         if (f[i].pump_in) {
             char *pd = static_cast<char *>(h->pump) + d.pump_off * es;
-            if (opt.precision == OPO_F64) host_to_state<double>(pd, f[i].pump_in, d.nt, st);
-            else host_to_state<float>(pd, f[i].pump_in, d.nt, st);
+            const long long count = static_cast<long long>(d.nt) * d.pump_windows;
+            if (opt.precision == OPO_F64) host_to_state<double>(pd, f[i].pump_in, count, st);
+            else host_to_state<float>(pd, f[i].pump_in, count, st);
         }
     }
+    set_counter<<<1, 1, 0, st>>>(h->d_counter, 0, 0);
     int krc = opt.precision == OPO_F64 ? setup_kernels<double>(h) : setup_kernels<float>(h);
     if (krc) return bail(krc);
     hipError_t le = hipGetLastError();
@@ -920,7 +937,7 @@ template <typename R> static int roundtrip_impl(opo_t *h, int n_rt)
     std::vector<double> chunk;
     while (done < n_rt) {
         const int m = std::min(kHistChunk, n_rt - done);
-        set_counter<<<1, 1, 0, h->stream>>>(h->d_counter, 0);
+        set_counter<<<1, 1, 0, h->stream>>>(h->d_counter, 0, -1);
         for (int r = 0; r < m; ++r) {
             if (h->graph) {
                 HIP_TRY(hipGraphLaunch(h->graph, h->stream));
@@ -1098,6 +1115,25 @@ int opo_get_energy_history(opo_t *h, int32_t inst, double *out, int32_t capacity
         for (int x = 0; x < 3; ++x)
             out[3 * r + x] = h->hist[(static_cast<size_t>(r) * h->n_inst + inst) * 3 + x];
     if (rows) *rows = h->hist_rows;
+    return OPO_OK;
+}
+
+int opo_get_record(opo_t *h, int32_t inst, int32_t field, int32_t rt, double *out)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    if (inst < 0 || inst >= h->n_inst || field < 0 || field >= h->inst[inst].nf || !out)
+        return fail(OPO_EINVAL, "bad instance, field or output pointer");
+    if (rt < 0 || rt >= std::min(h->record_cap, h->hist_rows))
+        return fail(OPO_EINVAL, "round trip " + std::to_string(rt) + " is not in the record (capacity " +
+                                    std::to_string(h->record_cap) + ", " + std::to_string(h->hist_rows) +
+                                    " round trips run)");
+    const InstDesc &d = h->inst[inst];
+    const long long elems = static_cast<long long>(h->state_bytes / h->elem);
+    const char *src = static_cast<const char *>(h->d_record) +
+                      (static_cast<long long>(rt) * elems + d.off + static_cast<long long>(field) * d.nt) * h->elem;
+    HIP_TRY(h->precision == OPO_F64 ? state_to_host<double>(out, src, d.nt, h->stream)
+                                    : state_to_host<float>(out, src, d.nt, h->stream));
     return OPO_OK;
 }
 

@@ -50,6 +50,8 @@ struct InstDesc {
     int tw4_bits;
     int res_mask, gdd_mask, eom_mask;
     int nf;               // coupled waves: 3 (p, s, i) or 2 (p, s; degenerate)
+    int pump_windows;     // > 1: round trip m reads window m of the input pump (zero after)
+    int pad0;
     double length_mm;
     double kappa[3];      // 1/mm per V/m; two waves: (kappa_p2, kappa_s, 0)
     double dk_rev;        // dk / (2 pi)  [rev/mm]
@@ -69,6 +71,7 @@ enum : int {
     A_MIRROR = 8,     // sqrt(R) e^{i delta} on resonant fields (Eq. 6)
     A_EOM = 16,       // EOM phase on the selected fields (Sec. 2.3)
     A_REFRESH = 32,   // input pump into a non-resonant pump, zero non-resonant s/i
+                      // (also: record the fields leaving the crystal with A_ENERGY)
     A_RK_THIS = 64,   // first half-step of this z-step
     A_FWD = 128,      // end with the forward column FFT + twiddle (else store samples)
 };
@@ -88,6 +91,10 @@ template <typename R> struct StepArgs {
     const double2 *tw4;       // four-step twiddle tables (FP64)
     const Phasor<R> *disp;    // linear-propagator tables H_x(k)/nt in row-pass order
     double *partial;          // [column tiles][3] energy partial sums
+    const int *counter;       // [0] energy-history slot, [1] round trips completed
+    cplx<R> *record;          // per-round-trip record of the fields leaving the crystal, or null
+    long long record_stride;  // elements per record slot (the whole state)
+    int record_cap;           // record slots
     int tile0;                // first tile of this launch (tiles are grouped by shape)
     int tile_count;           // tiles of this launch
     const int *block_map;     // mixed launches: workgroup -> tile (see mixed_pass)
@@ -349,6 +356,13 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     const V pcw = mk<V>(static_cast<R>(d.pump_cw[0]), static_cast<R>(d.pump_cw[1]));
     const bool imag = d.dk_rev == 0.0;   // couplings i kappa h/2 without a phase
     double en[3] = {0.0, 0.0, 0.0};
+    // round trips completed: the window of a long input pump that the refresh
+    // reads, and the record slot of the pass that A_ENERGY ends
+    const int rt = (flags & (A_REFRESH | A_ENERGY)) ? a.counter[1] : 0;
+    const bool rec = (flags & A_ENERGY) && a.record != nullptr && rt < a.record_cap && act;
+    V *rg = rec ? a.record + static_cast<long long>(rt) * a.record_stride + d.off + j1 : nullptr;
+    long long pwin = 0;                  // offset of the input-pump window, -1 = past the last
+    if (d.pump_windows > 1) pwin = rt < d.pump_windows ? static_cast<long long>(rt) * nt : -1;
 #pragma unroll
     for (int m = 0; m < PF; ++m) {
         const long long j = static_cast<long long>(j1) + static_cast<long long>(n1) * (t + m * T);
@@ -358,6 +372,12 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
             en[0] += static_cast<double>(y0.x) * y0.x + static_cast<double>(y0.y) * y0.y;
             en[1] += static_cast<double>(y1.x) * y1.x + static_cast<double>(y1.y) * y1.y;
             if constexpr (NF == 3) en[2] += static_cast<double>(y2.x) * y2.x + static_cast<double>(y2.y) * y2.y;
+        }
+        if (rec) {
+            const long long q = static_cast<long long>(n1) * (t + m * T);
+            rg[q] = y0;
+            rg[nt + q] = y1;
+            if constexpr (NF == 3) rg[2LL * nt + q] = y2;
         }
         if (flags & A_MIRROR) {
             if (d.res_mask & 1) y0 = pmul(y0, make_phasor<R>(d.mirror[0][0], d.mirror[0][1]));
@@ -375,7 +395,10 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
             if (NF == 3 && (d.eom_mask & 4)) y2 = pmul(y2, e);
         }
         if (flags & A_REFRESH) {
-            if (!(d.res_mask & 1)) y0 = (d.pump_off >= 0 && act) ? a.pump[d.pump_off + j] : pcw;
+            if (!(d.res_mask & 1)) {
+                if (d.pump_off < 0) y0 = pcw;
+                else y0 = (act && pwin >= 0) ? a.pump[d.pump_off + pwin + j] : mk<V>(R(0), R(0));
+            }
             if (!(d.res_mask & 2)) y1 = mk<V>(R(0), R(0));
             if (NF == 3 && !(d.res_mask & 4)) y2 = mk<V>(R(0), R(0));
         }
@@ -596,12 +619,19 @@ __global__ __launch_bounds__(kThreads) void energy_reduce(const InstDesc *inst, 
                 hist[(static_cast<long long>(slot) * n_inst + ii) * 3 + x] = e[x];
     }
     __syncthreads();
-    if (threadIdx.x == 0) *counter = slot + 1;
+    if (threadIdx.x == 0) {
+        counter[0] = slot + 1;
+        counter[1] += 1;      // round trips completed
+    }
 }
 
-__global__ void set_counter(int *counter, int v)
+// counter[0] = slot; counter[1] = rt unless rt < 0.
+__global__ void set_counter(int *counter, int slot, int rt)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *counter = v;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        counter[0] = slot;
+        if (rt >= 0) counter[1] = rt;
+    }
 }
 
 } // namespace opo

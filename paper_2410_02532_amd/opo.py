@@ -19,7 +19,8 @@ STATUS = {0: "OPO_OK", -1: "OPO_EINVAL", -2: "OPO_ENOMEM", -3: "OPO_EDEVICE",
 
 EXPORTS = ("opo_state_bytes", "opo_init", "opo_init_batch", "ssfm_propagate", "cavity_roundtrip",
            "opo_sync", "opo_get_fields", "opo_set_fields", "opo_get_energy_history",
-           "opo_get_grid", "opo_kernel_times", "opo_info", "opo_destroy", "opo_last_error")
+           "opo_get_record", "opo_get_grid", "opo_kernel_times", "opo_info", "opo_destroy",
+           "opo_last_error")
 KERNEL_CLASSES = ("column_pass", "row_pass", "energy_reduce", "mixed_pass")
 
 _d3 = ctypes.c_double * 3
@@ -31,7 +32,7 @@ class FieldsT(ctypes.Structure):
     _fields_ = [("nt", ctypes.c_int32), ("t_window_ps", ctypes.c_double), ("lambda_um", _d3),
                 ("n", _d3), ("init", ctypes.POINTER(ctypes.c_double)),
                 ("pump_in", ctypes.POINTER(ctypes.c_double)), ("pump_cw", _d2),
-                ("n_fields", ctypes.c_int32)]
+                ("n_fields", ctypes.c_int32), ("pump_windows", ctypes.c_int32)]
 
 
 class CrystalT(ctypes.Structure):
@@ -52,7 +53,7 @@ class OptionsT(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("state", ctypes.c_void_p),
                 ("state_bytes", ctypes.c_uint64), ("tile_a", ctypes.c_int32),
                 ("tile_b", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("profile", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("record_rt", ctypes.c_int32)]
 
 
 class OpoError(RuntimeError):
@@ -86,6 +87,7 @@ def load():
     lib.opo_get_fields.argtypes = [P, I, I, I, P]
     lib.opo_set_fields.argtypes = [P, I, I, P]
     lib.opo_get_energy_history.argtypes = [P, I, P, I, ctypes.POINTER(I)]
+    lib.opo_get_record.argtypes = [P, I, I, I, P]
     lib.opo_get_grid.argtypes = [P, I, P, P]
     lib.opo_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(D)]
     lib.opo_kernel_times.argtypes = [P, P, P]
@@ -93,7 +95,8 @@ def load():
     lib.opo_last_error.argtypes = []
     lib.opo_last_error.restype = ctypes.c_char_p
     for name in ("opo_init", "opo_init_batch", "ssfm_propagate", "cavity_roundtrip", "opo_sync",
-                 "opo_get_fields", "opo_set_fields", "opo_get_energy_history", "opo_get_grid",
+                 "opo_get_fields", "opo_set_fields", "opo_get_energy_history", "opo_get_record",
+                 "opo_get_grid",
                  "opo_kernel_times", "opo_info", "opo_destroy"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -128,7 +131,13 @@ def _structs(instances, nz):
         keep.append(init)
         f.init = init.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
         pump = np.asarray(ins.get("pump_in", 0.0), dtype=np.complex128)
-        if pump.ndim == 0 or np.all(pump == pump.flat[0]):
+        if pump.ndim == 2:                  # (windows, nt): one window per round trip
+            pump = np.ascontiguousarray(pump.reshape(-1, f.nt))
+            keep.append(pump)
+            f.pump_in = pump.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            f.pump_windows = pump.shape[0]
+            f.pump_cw = _d2(0.0, 0.0)
+        elif pump.ndim == 0 or np.all(pump == pump.flat[0]):
             v = complex(pump.flat[0]) if pump.size else 0j
             f.pump_in = ctypes.POINTER(ctypes.c_double)()
             f.pump_cw = _d2(v.real, v.imag)
@@ -163,13 +172,15 @@ class Opo:
 
     instances: list of dicts with keys crystal, cavity, fields (nf, nt), pump_in; the
     crystal's ``nf`` (default 3) selects three coupled waves or the two-wave degenerate
-    model.
+    model. pump_in of shape (windows, nt) is a long pump read one window per round trip.
+    record_rt > 0 keeps the fields leaving the crystal for the first record_rt round trips
+    (read with record()).
     The field state lives in a torch uint8 tensor on ``device``; the library
     runs on a torch stream (default priority) created for the handle.
     """
 
     def __init__(self, instances, nz, precision="f32", device=0, tile_a=0, tile_b=0,
-                 use_graph=True, profile=False):
+                 use_graph=True, profile=False, record_rt=0):
         import torch
         lib = load()
         self._lib = lib
@@ -187,7 +198,7 @@ class Opo:
                        stream=ctypes.c_void_p(self._stream.cuda_stream),
                        state=ctypes.c_void_p(self._state.data_ptr()), state_bytes=nbytes,
                        tile_a=int(tile_a), tile_b=int(tile_b), use_graph=1 if use_graph else -1,
-                       profile=1 if profile else 0)
+                       profile=1 if profile else 0, record_rt=int(record_rt))
         h = ctypes.c_void_p()
         _check(lib.opo_init_batch(ctypes.byref(h), self.n, fields, crystals, cavities,
                                   ctypes.byref(opt)))
@@ -227,6 +238,16 @@ class Opo:
         if rows.value:
             _check(self._lib.opo_get_energy_history(self.h, inst, out.ctypes.data, rows.value,
                                                     ctypes.byref(rows)))
+        return out
+
+    def record(self, rt, inst=0):
+        """Fields (nf, nt) of instance inst as they left the crystal in round trip rt."""
+        nt, nf = self.nts[inst], self.nfs[inst]
+        out = np.empty((nf, nt), dtype=np.complex128)
+        for x in range(nf):
+            buf = np.empty(nt, dtype=np.complex128)
+            _check(self._lib.opo_get_record(self.h, inst, x, int(rt), buf.ctypes.data))
+            out[x] = buf
         return out
 
     def grid(self, inst=0):
