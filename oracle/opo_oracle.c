@@ -41,6 +41,11 @@
  *     pump and non-resonant signal/idler start at zero; after the pass the
  *     energies sum_j |A_x(t_j)|^2 are recorded, then GDD, then
  *     sqrt(R_x) e^{i delta_x} on resonant fields, then the EOM phase.
+ *   - Resonant pump (pump-resonant and triply resonant cavities): the paper
+ *     leaves the pump injection unprinted. At the start of every round trip
+ *     the input pump couples in through the pump mirror, A_p += sqrt(1 - R_p)
+ *     A_in, while sqrt(R_p) e^{i delta_p} acts on the circulating pump at the
+ *     end of the round trip like on any resonant field.
  *   - Nanosecond regime: the input pump is a long record of n_slices
  *     consecutive windows of nt samples; round trip m reads window m into a
  *     non-resonant pump, and a zero pump once the record is exhausted. The
@@ -344,12 +349,18 @@ static void roundtrips(const ora_crystal *c, const ora_cavity *cav, cplx *a,
     int n = c->nt;
     double dz = c->length_mm / (double)nz;
     for (int m = 0; m < n_rt; m++) {
+        int w = same_pump ? 0 : m;
         if (!cav->resonant[0]) {
-            int w = same_pump ? 0 : m;
             if (w < n_slices)
                 memcpy(a, pump_in + (size_t)w * n, sizeof(cplx) * (size_t)n);
             else
                 memset(a, 0, sizeof(cplx) * (size_t)n);
+        } else if (w < n_slices) {
+            /* resonant pump: the input couples in through a mirror of
+             * transmission 1 - R_p */
+            double t = sqrt(1.0 - cav->refl[0]);
+            for (int j = 0; j < n; j++)
+                a[j] += t * pump_in[(size_t)w * n + j];
         }
         for (int x = 1; x < c->nf; x++)
             if (!cav->resonant[x])
