@@ -98,7 +98,10 @@ typedef struct {
 typedef struct {
     int32_t resonant[3];    /* 1 = field is fed back (Eq. 6); a non-resonant pump
                                is re-read from the input, a non-resonant signal or
-                               idler restarts from zero                           */
+                               idler restarts from zero. A resonant pump (pump-
+                               enhanced or triply resonant cavities) receives the
+                               input through its mirror at the start of every
+                               round trip: A_p += sqrt(1 - R_p) A_in              */
     double refl[3];         /* R_x = 1 - theta_x in [0, 1] (resonant fields)      */
     double delta_rad[3];    /* detuning phase delta_x per round trip              */
     double gdd_fs2;         /* chirped-mirror GDD gamma: spectrum * e^{i gamma w^2/2} */

@@ -664,6 +664,8 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         d.eom_rev_step = k[i].eom_fpm_thz * T / d.nt;          // f dt
         d.pump_cw[0] = f[i].pump_cw[0];
         d.pump_cw[1] = f[i].pump_cw[1];
+        // a resonant pump: the input couples in through the pump mirror
+        d.inject = k[i].resonant[0] ? std::sqrt(1.0 - k[i].refl[0]) : 0.0;
 
     }
 

@@ -62,6 +62,7 @@ struct InstDesc {
     double eom_beta;      // EOM phase = beta sin(2 pi rho_j), rho_j = eom_rev0 + eom_rev_step j
     double eom_rev0, eom_rev_step;
     double pump_cw[2];
+    double inject;        // resonant pump: input coupled in per round trip, sqrt(1 - R_p)
 };
 
 enum : int {
@@ -395,10 +396,10 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
             if (NF == 3 && (d.eom_mask & 4)) y2 = pmul(y2, e);
         }
         if (flags & A_REFRESH) {
-            if (!(d.res_mask & 1)) {
-                if (d.pump_off < 0) y0 = pcw;
-                else y0 = (act && pwin >= 0) ? a.pump[d.pump_off + pwin + j] : mk<V>(R(0), R(0));
-            }
+            V pin = pcw;                 // input pump sample of this round trip
+            if (d.pump_off >= 0) pin = (act && pwin >= 0) ? a.pump[d.pump_off + pwin + j] : mk<V>(R(0), R(0));
+            if (!(d.res_mask & 1)) y0 = pin;
+            else if (d.inject != 0.0) y0 = cadd(y0, pmul(pin, make_phasor<R>(d.inject, 0.0)));
             if (!(d.res_mask & 2)) y1 = mk<V>(R(0), R(0));
             if (NF == 3 && !(d.res_mask & 4)) y2 = mk<V>(R(0), R(0));
         }
