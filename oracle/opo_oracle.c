@@ -19,6 +19,7 @@
  *   Sec. 2.3   intracavity GDD and EOM                      -> ora_gdd, ora_eom
  *   Sec. 4.1   main loop: pump read, pass, GDD, phase, EOM  -> ora_roundtrips
  *   Sec. 2.4   degenerate signal equation (two waves)        -> cwe2_rhs
+ *   Sec. 1     Kerr term named as an extension                -> kerr_rhs
  *   Sec. 4.1   nanosecond regime: long pump read slice by slice,
  *              per-round-trip output record (ReadPump,
  *              SaveRoundTrip)                                -> ora_roundtrips_rec
@@ -41,6 +42,11 @@
  *     pump and non-resonant signal/idler start at zero; after the pass the
  *     energies sum_j |A_x(t_j)|^2 are recorded, then GDD, then
  *     sqrt(R_x) e^{i delta_x} on resonant fields, then the EOM phase.
+ *   - Kerr term (the chi(3) extension the paper names as a simple addition,
+ *     in the coupled nonlinear Schroedinger form): each field gains
+ *     i gamma_x (|A_x|^2 + 2 sum_{y != x} |A_y|^2) A_x in the nonlinear
+ *     operator, gamma_x = (2 pi / lambda_x) n2 (n_x eps0 c / 2), so that the
+ *     self-phase per length is k0 n2 I with I = n eps0 c |A|^2 / 2.
  *   - Resonant pump (pump-resonant and triply resonant cavities): the paper
  *     leaves the pump injection unprinted. At the start of every round trip
  *     the input pump couples in through the pump mirror, A_p += sqrt(1 - R_p)
@@ -86,6 +92,7 @@ typedef struct {
     double db1_ps_per_mm[3];
     double b2_fs2_per_mm[3];
     double b3_fs3_per_mm[3];
+    double n2_m2_per_w;    /* Kerr (chi(3)) nonlinear index, 0 = none       */
 } ora_crystal;
 
 typedef struct {
@@ -206,12 +213,39 @@ static void cwe2_rhs(const double kap[3], cplx ph, cplx ap, cplx as, cplx out[3]
     out[2] = 0.0;
 }
 
-static void rhs(int nf, const double kap[3], cplx ph, const cplx y[3], cplx out[3])
+/* Kerr coefficients gamma_x in 1/mm per (V/m)^2 (0 without n2). */
+void ora_kerr(const ora_crystal *c, double gamma[3])
+{
+    const double eps0 = 8.8541878128e-12, c0 = 299792458.0;
+    for (int x = 0; x < 3; x++)
+        gamma[x] = 2.0 * ORA_PI / (c->lambda_um[x] * 1e-6) * c->n2_m2_per_w *
+                   (0.5 * c->n[x] * eps0 * c0) * 1e-3;
+}
+
+/* Self- and cross-phase modulation of the nf fields, added to out. */
+static void kerr_rhs(int nf, const double gam[3], const cplx y[3], cplx out[3])
+{
+    double p[3] = {0.0, 0.0, 0.0};
+    for (int x = 0; x < nf; x++)
+        p[x] = creal(y[x]) * creal(y[x]) + cimag(y[x]) * cimag(y[x]);
+    for (int x = 0; x < nf; x++) {
+        double phi = p[x];
+        for (int o = 0; o < nf; o++)
+            if (o != x)
+                phi += 2.0 * p[o];
+        out[x] += I * gam[x] * phi * y[x];
+    }
+}
+
+static void rhs(int nf, const double kap[3], const double gam[3], int kerr, cplx ph,
+                const cplx y[3], cplx out[3])
 {
     if (nf == 2)
         cwe2_rhs(kap, ph, y[0], y[1], out);
     else
         cwe_rhs(kap, ph, y[0], y[1], y[2], out);
+    if (kerr)
+        kerr_rhs(nf, gam, y, out);
 }
 
 /* One classical RK4 step of size h from z0 for all time points of the
@@ -219,8 +253,10 @@ static void rhs(int nf, const double kap[3], cplx ph, const cplx y[3], cplx out[
 void ora_rk4(const ora_crystal *c, cplx *a, double z0, double h)
 {
     int n = c->nt, nf = c->nf;
-    double kap[3];
+    double kap[3], gam[3];
     ora_kappa(c, kap);
+    ora_kerr(c, gam);
+    int kerr = c->n2_m2_per_w != 0.0;
     cplx ph0 = cexp(I * c->dk_per_mm * z0);
     cplx ph1 = cexp(I * c->dk_per_mm * (z0 + 0.5 * h));
     cplx ph2 = cexp(I * c->dk_per_mm * (z0 + h));
@@ -229,16 +265,16 @@ void ora_rk4(const ora_crystal *c, cplx *a, double z0, double h)
         for (int x = 0; x < nf; x++)
             y[x] = a[x * n + j];
         cplx k1[3], k2[3], k3[3], k4[3], t[3];
-        rhs(nf, kap, ph0, y, k1);
+        rhs(nf, kap, gam, kerr, ph0, y, k1);
         for (int x = 0; x < 3; x++)
             t[x] = y[x] + 0.5 * h * k1[x];
-        rhs(nf, kap, ph1, t, k2);
+        rhs(nf, kap, gam, kerr, ph1, t, k2);
         for (int x = 0; x < 3; x++)
             t[x] = y[x] + 0.5 * h * k2[x];
-        rhs(nf, kap, ph1, t, k3);
+        rhs(nf, kap, gam, kerr, ph1, t, k3);
         for (int x = 0; x < 3; x++)
             t[x] = y[x] + h * k3[x];
-        rhs(nf, kap, ph2, t, k4);
+        rhs(nf, kap, gam, kerr, ph2, t, k4);
         for (int x = 0; x < nf; x++)
             a[x * n + j] = y[x] + h / 6.0 * (k1[x] + 2.0 * k2[x] + 2.0 * k3[x] + k4[x]);
     }

@@ -34,13 +34,14 @@ class Crystal(ctypes.Structure):
         ("db1_ps_per_mm", _c3),
         ("b2_fs2_per_mm", _c3),
         ("b3_fs3_per_mm", _c3),
+        ("n2_m2_per_w", ctypes.c_double),
     ]
 
     @classmethod
     def from_dict(cls, d):
         c = cls()
         for name, ctype in cls._fields_:
-            v = d.get(name, 3) if name == "nf" else d[name]
+            v = d.get(name, 3) if name == "nf" else d.get(name, 0.0) if name == "n2_m2_per_w" else d[name]
             if ctype in (_c3,):
                 setattr(c, name, _c3(*[float(x) for x in v]))
             elif ctype is ctypes.c_int:
@@ -99,6 +100,7 @@ def _load():
         lib.ora_omega.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double]
         lib.ora_omega.restype = ctypes.c_double
         lib.ora_kappa.argtypes = [ctypes.POINTER(Crystal), P]
+        lib.ora_kerr.argtypes = [ctypes.POINTER(Crystal), P]
         lib.ora_dispersion.argtypes = [ctypes.POINTER(Crystal), ctypes.c_int, ctypes.c_double, P]
         lib.ora_rk4.argtypes = [ctypes.POINTER(Crystal), P, ctypes.c_double, ctypes.c_double]
         lib.ora_linear.argtypes = [ctypes.POINTER(Crystal), P, ctypes.c_double]
@@ -160,6 +162,13 @@ def omega(n, t_window_ps):
 def kappa(crystal):
     out = np.zeros(3)
     _load().ora_kappa(ctypes.byref(Crystal.from_dict(crystal)), _ptr(out))
+    return out
+
+
+def kerr(crystal):
+    """Kerr coefficients gamma_x [1/mm per (V/m)^2]."""
+    out = np.zeros(3)
+    _load().ora_kerr(ctypes.byref(Crystal.from_dict(crystal)), _ptr(out))
     return out
 
 
