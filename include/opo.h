@@ -92,6 +92,10 @@ typedef struct {
     double db1_ps_per_mm[3];/* 1/v_x - 1/v_s                                      */
     double b2_fs2_per_mm[3];/* GVD k''_x                                          */
     double b3_fs3_per_mm[3];/* TOD k'''_x                                         */
+    double n2_m2_per_w;     /* Kerr index n2 [m^2/W], 0 = none: the nonlinear step
+                               adds i gamma_x (|A_x|^2 + 2 sum_{y != x} |A_y|^2) A_x
+                               with gamma_x = (2 pi/lambda_x) n2 (n_x eps0 c/2),
+                               the chi(3) extension the paper names (Sec. 1)      */
 } opo_crystal_t;
 
 /* Cavity: Eq. 6 and the Sec. 2.3 elements, applied after every pass. */

@@ -253,6 +253,7 @@ static int validate(int n, const opo_fields_t *f, const opo_crystal_t *c, const 
         if (c[i].nz < 1) return fail(OPO_EINVAL, at + "nz must be >= 1");
         if (c[i].nz != c[0].nz) return fail(OPO_EINVAL, at + "all instances must share nz");
         if (!std::isfinite(c[i].deff_pm_per_v) || !std::isfinite(c[i].dk_per_mm) ||
+            !std::isfinite(c[i].n2_m2_per_w) ||
             !finite3(c[i].alpha_per_mm) || !finite3(c[i].db1_ps_per_mm) ||
             !finite3(c[i].b2_fs2_per_mm) || !finite3(c[i].b3_fs3_per_mm))
             return fail(OPO_EINVAL, at + "crystal coefficients must be finite");
@@ -666,6 +667,11 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         d.pump_cw[1] = f[i].pump_cw[1];
         // a resonant pump: the input couples in through the pump mirror
         d.inject = k[i].resonant[0] ? std::sqrt(1.0 - k[i].refl[0]) : 0.0;
+        // Kerr term: gamma_x = (2 pi/lambda_x) n2 (n_x eps0 c/2), per mm
+        d.kerr = c[i].n2_m2_per_w != 0.0;
+        for (int x = 0; x < 3; ++x)
+            d.gamma[x] = kTwoPi / (f[i].lambda_um[x] * 1e-6) * c[i].n2_m2_per_w *
+                         (0.5 * f[i].n[x] * 8.8541878128e-12 * 299792458.0) * 1e-3;
 
     }
 

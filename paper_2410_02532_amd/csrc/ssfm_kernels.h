@@ -51,7 +51,7 @@ struct InstDesc {
     int res_mask, gdd_mask, eom_mask;
     int nf;               // coupled waves: 3 (p, s, i) or 2 (p, s; degenerate)
     int pump_windows;     // > 1: round trip m reads window m of the input pump (zero after)
-    int pad0;
+    int kerr;             // Kerr term on (gamma below)
     double length_mm;
     double kappa[3];      // 1/mm per V/m; two waves: (kappa_p2, kappa_s, 0)
     double dk_rev;        // dk / (2 pi)  [rev/mm]
@@ -63,6 +63,7 @@ struct InstDesc {
     double eom_rev0, eom_rev_step;
     double pump_cw[2];
     double inject;        // resonant pump: input coupled in per round trip, sqrt(1 - R_p)
+    double gamma[3];      // Kerr coefficients [1/mm per (V/m)^2]
 };
 
 enum : int {
@@ -165,6 +166,7 @@ __device__ __forceinline__ Phasor<R> twiddle4(const double2 *__restrict__ t, int
 // e^{+i dk z}, i kappa_i e^{+i dk z}) * h/2 at z0, z0 + h/2, z0 + h.
 template <typename R> struct Coupling {
     cplx<R> c[2][3][3];   // [previous / this half-step][stage position][field]
+    R g[3];               // Kerr coefficients gamma_x h/2
 };
 
 // Computed by six threads in FP64 and shared through LDS.
@@ -186,6 +188,7 @@ __device__ __forceinline__ void coupling_tile(const InstDesc &d, double z_prev, 
         out->c[which][st][0] = mk<V>(static_cast<R>(kp * sn), static_cast<R>(kp * cs));
         out->c[which][st][1] = mk<V>(static_cast<R>(-ks * sn), static_cast<R>(ks * cs));
         out->c[which][st][2] = mk<V>(static_cast<R>(-ki * sn), static_cast<R>(ki * cs));
+        if (q < 3) out->g[q] = static_cast<R>(d.gamma[q] * hh);
     }
 }
 
@@ -256,11 +259,73 @@ __device__ __forceinline__ void rk4_point2(const cplx<R> (&c)[3][3], cplx<R> &ap
                as.y + third * (s1.y + two * (s2.y + s3.y) + s4.y));
 }
 
+// Kerr terms times h/2 added to the stage slopes f: i g_x (|A_x|^2 + 2 sum_{y != x}
+// |A_y|^2) A_x (self- and cross-phase modulation, the chi(3) extension of the
+// nonlinear operator).
+template <typename R, int NF>
+__device__ __forceinline__ void kerr_add(const R (&g)[3], const cplx<R> (&y)[3], cplx<R> (&f)[3])
+{
+    R p[NF];
+#pragma unroll
+    for (int x = 0; x < NF; ++x) p[x] = y[x].x * y[x].x + y[x].y * y[x].y;
+    R tot = R(0);
+#pragma unroll
+    for (int x = 0; x < NF; ++x) tot += p[x];
+#pragma unroll
+    for (int x = 0; x < NF; ++x) {
+        const R w = g[x] * (R(2) * tot - p[x]);
+        f[x].x -= w * y[x].y;
+        f[x].y += w * y[x].x;
+    }
+}
+
+// RK4 half-step with the Kerr terms (general coupling coefficients).
+template <typename R, int NF>
+__device__ __forceinline__ void rk4_kerr(const cplx<R> (&c)[3][3], const R (&g)[3], cplx<R> &y0, cplx<R> &y1,
+                                         cplx<R> &y2)
+{
+    using V = cplx<R>;
+    const V y[3] = {y0, y1, y2};
+    V k[4][3], t[3];
+    auto slope = [&](int st, const V (&in)[3], V (&out)[3]) {
+        if constexpr (NF == 3) cwe_rhs<false>(c[st], in[0], in[1], in[2], out[0], out[1], out[2]);
+        else {
+            cwe2_rhs<false>(c[st], in[0], in[1], out[0], out[1]);
+            out[2] = mk<V>(R(0), R(0));
+        }
+        kerr_add<R, NF>(g, in, out);
+    };
+    const R two = R(2), third = R(1) / R(3);
+    slope(0, y, k[0]);
+#pragma unroll
+    for (int x = 0; x < 3; ++x) t[x] = cadd(y[x], k[0][x]);
+    slope(1, t, k[1]);
+#pragma unroll
+    for (int x = 0; x < 3; ++x) t[x] = cadd(y[x], k[1][x]);
+    slope(1, t, k[2]);
+#pragma unroll
+    for (int x = 0; x < 3; ++x) t[x] = mk<V>(y[x].x + two * k[2][x].x, y[x].y + two * k[2][x].y);
+    slope(2, t, k[3]);
+    V r[3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+        r[x] = mk<V>(y[x].x + third * (k[0][x].x + two * (k[1][x].x + k[2][x].x) + k[3][x].x),
+                     y[x].y + third * (k[0][x].y + two * (k[1][x].y + k[2][x].y) + k[3][x].y));
+    y0 = r[0];
+    y1 = r[1];
+    if constexpr (NF == 3) y2 = r[2];
+}
+
 // RK4 half-step of the NF coupled waves at one time point (y2 unused for two).
 template <typename R, int NF>
-__device__ __forceinline__ void rk4_fields(const cplx<R> (&c)[3][3], bool imag, cplx<R> &y0, cplx<R> &y1,
-                                           cplx<R> &y2)
+__device__ __forceinline__ void rk4_fields(const Coupling<R> &cp, int which, bool imag, bool kerr, cplx<R> &y0,
+                                           cplx<R> &y1, cplx<R> &y2)
 {
+    const cplx<R>(&c)[3][3] = cp.c[which];
+    if (kerr) {
+        rk4_kerr<R, NF>(c, cp.g, y0, y1, y2);
+        return;
+    }
     if constexpr (NF == 3) {
         if (imag) rk4_point<R, true>(c, y0, y1, y2);
         else rk4_point<R, false>(c, y0, y1, y2);
@@ -356,6 +421,7 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
 
     const V pcw = mk<V>(static_cast<R>(d.pump_cw[0]), static_cast<R>(d.pump_cw[1]));
     const bool imag = d.dk_rev == 0.0;   // couplings i kappa h/2 without a phase
+    const bool kerr = d.kerr != 0;
     double en[3] = {0.0, 0.0, 0.0};
     // round trips completed: the window of a long input pump that the refresh
     // reads, and the record slot of the pass that A_ENERGY ends
@@ -368,7 +434,7 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     for (int m = 0; m < PF; ++m) {
         const long long j = static_cast<long long>(j1) + static_cast<long long>(n1) * (t + m * T);
         V y0 = v[0][m], y1 = v[1][m], y2 = v[NF - 1][m];
-        if (flags & A_RK_PREV) rk4_fields<R, NF>(cpl->c[0], imag, y0, y1, y2);
+        if (flags & A_RK_PREV) rk4_fields<R, NF>(*cpl, 0, imag, kerr, y0, y1, y2);
         if ((flags & A_ENERGY) && act) {
             en[0] += static_cast<double>(y0.x) * y0.x + static_cast<double>(y0.y) * y0.y;
             en[1] += static_cast<double>(y1.x) * y1.x + static_cast<double>(y1.y) * y1.y;
@@ -403,7 +469,7 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
             if (!(d.res_mask & 2)) y1 = mk<V>(R(0), R(0));
             if (NF == 3 && !(d.res_mask & 4)) y2 = mk<V>(R(0), R(0));
         }
-        if (flags & A_RK_THIS) rk4_fields<R, NF>(cpl->c[1], imag, y0, y1, y2);
+        if (flags & A_RK_THIS) rk4_fields<R, NF>(*cpl, 1, imag, kerr, y0, y1, y2);
         v[0][m] = y0;
         v[1][m] = y1;
         if constexpr (NF == 3) v[2][m] = y2;

@@ -39,7 +39,7 @@ class CrystalT(ctypes.Structure):
     _fields_ = [("length_mm", ctypes.c_double), ("nz", ctypes.c_int32),
                 ("deff_pm_per_v", ctypes.c_double), ("dk_per_mm", ctypes.c_double),
                 ("alpha_per_mm", _d3), ("db1_ps_per_mm", _d3), ("b2_fs2_per_mm", _d3),
-                ("b3_fs3_per_mm", _d3)]
+                ("b3_fs3_per_mm", _d3), ("n2_m2_per_w", ctypes.c_double)]
 
 
 class CavityT(ctypes.Structure):
@@ -155,6 +155,7 @@ def _structs(instances, nz):
         c.db1_ps_per_mm = _d3(*cr["db1_ps_per_mm"])
         c.b2_fs2_per_mm = _d3(*cr["b2_fs2_per_mm"])
         c.b3_fs3_per_mm = _d3(*cr["b3_fs3_per_mm"])
+        c.n2_m2_per_w = float(cr.get("n2_m2_per_w", 0.0))
         k = cavities[i]
         k.resonant = _i3(*[int(v) for v in cav["resonant"]])
         k.refl = _d3(*cav["refl"])
