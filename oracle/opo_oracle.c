@@ -20,6 +20,7 @@
  *   Sec. 4.1   main loop: pump read, pass, GDD, phase, EOM  -> ora_roundtrips
  *   Sec. 2.4   degenerate signal equation (two waves)        -> cwe2_rhs
  *   Sec. 1     Kerr term named as an extension                -> kerr_rhs
+ *   Sec. 1     several crystals per round trip               -> ora_roundtrips_multi
  *   Sec. 4.1   nanosecond regime: long pump read slice by slice,
  *              per-round-trip output record (ReadPump,
  *              SaveRoundTrip)                                -> ora_roundtrips_rec
@@ -42,6 +43,10 @@
  *     pump and non-resonant signal/idler start at zero; after the pass the
  *     energies sum_j |A_x(t_j)|^2 are recorded, then GDD, then
  *     sqrt(R_x) e^{i delta_x} on resonant fields, then the EOM phase.
+ *   - Several crystals per round trip (an extension the paper names): the
+ *     fields pass them in order, each crystal with its own parameters, step
+ *     count and z measured from its own entrance (so its e^{i dk z} starts at
+ *     1); nothing acts between them, and the boundary follows the last.
  *   - Kerr term (the chi(3) extension the paper names as a simple addition,
  *     in the coupled nonlinear Schroedinger form): each field gains
  *     i gamma_x (|A_x|^2 + 2 sum_{y != x} |A_y|^2) A_x in the nonlinear
@@ -378,12 +383,12 @@ void ora_eom(cplx *field, int n, double t_window_ps, double beta, double fpm_thz
  * window m (m < n_slices) into a non-resonant pump, else a zero pump.
  * record, if not NULL, receives window m of every field as it leaves the
  * crystal: record[(m*nf + x)*nt + j]. energy[m*3+x] as ora_roundtrips. */
-static void roundtrips(const ora_crystal *c, const ora_cavity *cav, cplx *a,
-                       const cplx *pump_in, int n_slices, int same_pump, int nz, int n_rt,
+static void roundtrips(const ora_crystal *cs, int n_cryst, const int *nzs, const ora_cavity *cav,
+                       cplx *a, const cplx *pump_in, int n_slices, int same_pump, int n_rt,
                        double *energy, cplx *record)
 {
+    const ora_crystal *c = cs;   /* grid and field count: the same in every crystal */
     int n = c->nt;
-    double dz = c->length_mm / (double)nz;
     for (int m = 0; m < n_rt; m++) {
         int w = same_pump ? 0 : m;
         if (!cav->resonant[0]) {
@@ -402,7 +407,9 @@ static void roundtrips(const ora_crystal *c, const ora_cavity *cav, cplx *a,
             if (!cav->resonant[x])
                 memset(a + (size_t)x * n, 0, sizeof(cplx) * (size_t)n);
 
-        ora_pass(c, a, nz, dz, 0.0);
+        /* the crystals of the round trip in order, each from its own entrance */
+        for (int k = 0; k < n_cryst; k++)
+            ora_pass(cs + k, a, nzs[k], cs[k].length_mm / (double)nzs[k], 0.0);
 
         if (record)
             memcpy(record + (size_t)m * c->nf * n, a, sizeof(cplx) * (size_t)c->nf * n);
@@ -437,7 +444,17 @@ void ora_roundtrips_rec(const ora_crystal *c, const ora_cavity *cav, cplx *a,
                         const cplx *pump_in, int n_slices, int nz, int n_rt,
                         double *energy, cplx *record)
 {
-    roundtrips(c, cav, a, pump_in, n_slices, 0, nz, n_rt, energy, record);
+    roundtrips(c, 1, &nz, cav, a, pump_in, n_slices, 0, n_rt, energy, record);
+}
+
+/* Round trips through n_cryst crystals in sequence (crystal k with nzs[k]
+ * steps of its own L/nz, z from its own entrance), then the boundary as in
+ * ora_roundtrips_rec. Every crystal has the grid and field count of the first. */
+void ora_roundtrips_multi(const ora_crystal *cs, int n_cryst, const int *nzs,
+                          const ora_cavity *cav, cplx *a, const cplx *pump_in, int n_slices,
+                          int n_rt, double *energy, cplx *record)
+{
+    roundtrips(cs, n_cryst, nzs, cav, a, pump_in, n_slices, 0, n_rt, energy, record);
 }
 
 /* n_rt cavity round trips (Sec. 4.1 main loop with Eq. 6) with the same
@@ -446,5 +463,5 @@ void ora_roundtrips_rec(const ora_crystal *c, const ora_cavity *cav, cplx *a,
 void ora_roundtrips(const ora_crystal *c, const ora_cavity *cav, cplx *a,
                     const cplx *pump_in, int nz, int n_rt, double *energy)
 {
-    roundtrips(c, cav, a, pump_in, 1, 1, nz, n_rt, energy, NULL);
+    roundtrips(c, 1, &nz, cav, a, pump_in, 1, 1, n_rt, energy, NULL);
 }

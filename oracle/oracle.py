@@ -113,6 +113,9 @@ def _load():
                                        ctypes.c_int, ctypes.c_int, P]
         lib.ora_roundtrips_rec.argtypes = [ctypes.POINTER(Crystal), ctypes.POINTER(Cavity), P, P,
                                            ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
+        lib.ora_roundtrips_multi.argtypes = [ctypes.POINTER(Crystal), ctypes.c_int, P,
+                                             ctypes.POINTER(Cavity), P, P, ctypes.c_int,
+                                             ctypes.c_int, P, P]
         _lib = lib
     return _lib
 
@@ -246,4 +249,26 @@ def roundtrips_record(crystal, cavity, a, pump_long, nz, n_rt, record=True):
                                ctypes.byref(Cavity.from_dict(cavity)), _ptr(a), _ptr(p),
                                p.size // nt, int(nz), int(n_rt), _ptr(e),
                                _ptr(rec) if record else None)
+    return a, e, rec
+
+
+def roundtrips_multi(crystals, nzs, cavity, a, pump_in, n_rt, record=False):
+    """Round trips through the crystals in order (crystal k with nzs[k] steps). pump_in is
+    (nt,) for the same pump every round trip or (windows, nt). Returns (fields,
+    energies[n_rt, 3], record or None)."""
+    c0 = crystals[0]
+    nt = c0["nt"]
+    nf = _nf(c0)
+    a = _fields(a, c0)
+    p = np.asarray(pump_in, dtype=np.complex128)
+    if p.ndim == 1:
+        p = np.broadcast_to(p, (int(n_rt), nt))
+    p = _cplx(p.reshape(-1))
+    arr = (Crystal * len(crystals))(*[Crystal.from_dict(c) for c in crystals])
+    nz_arr = np.ascontiguousarray(nzs, dtype=np.intc)
+    e = np.zeros((int(n_rt), 3))
+    rec = np.zeros((int(n_rt), nf, nt), dtype=np.complex128) if record else None
+    _load().ora_roundtrips_multi(arr, len(crystals), _ptr(nz_arr), ctypes.byref(Cavity.from_dict(cavity)),
+                                 _ptr(a), _ptr(p), p.size // nt, int(n_rt), _ptr(e),
+                                 _ptr(rec) if record else None)
     return a, e, rec
