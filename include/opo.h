@@ -143,6 +143,13 @@ typedef struct {
                                pass, before GDD and the mirror; Sec. 4.1 round-
                                trip save), read with opo_get_record. Costs
                                record_rt * opo_state_bytes() of device memory     */
+    int32_t n_crystals;     /* crystals per round trip, K >= 1 (0 = 1): the crystal
+                               array of opo_init_batch then holds n*K entries,
+                               instance-major (crystals[i*K + k] is crystal k of
+                               instance i); the fields pass them in order, each
+                               with its own nz (shared by the instances) and z
+                               from its own entrance, and the boundary follows
+                               the last; ssfm_propagate uses crystal 0            */
 } opo_options_t;
 
 /* Device bytes of field state for n instances (n_fields * nt complex values

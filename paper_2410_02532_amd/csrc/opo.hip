@@ -147,7 +147,9 @@ struct opo_s {
     int precision = OPO_F32;
     int device = 0;
     int n_inst = 0;
-    int nz = 1;
+    int nz = 1;                      // steps of the first crystal
+    int n_stage = 1;                 // crystals per round trip
+    std::vector<int> stage_nz;       // steps per pass of each crystal
     hipStream_t stream = nullptr;
     bool own_stream = false;
     void *state = nullptr;
@@ -225,7 +227,31 @@ static void coupling(const opo_fields_t &f, double deff, double kappa[3])
     }
 }
 
-static int validate(int n, const opo_fields_t *f, const opo_crystal_t *c, const opo_cavity_t *k,
+// Crystal-dependent descriptor fields: length, couplings (Sec. 2.1), the
+// Eq. 5 dispersion coefficients, loss, mismatch and the Kerr coefficients.
+static void set_crystal(InstDesc &d, const opo_fields_t &f, const opo_crystal_t &c)
+{
+    const double T = f.t_window_ps;
+    d.length_mm = c.length_mm;
+    coupling(f, c.deff_pm_per_v, d.kappa);
+    for (int x = 0; x < 3; ++x) {
+        // Eq. 5 phase per mm in revolutions for bin ks (w = 2 pi ks/T):
+        // (-db1 w + b2 w^2/2 - b3 w^3/6)/(2 pi)
+        const double b2 = c.b2_fs2_per_mm[x] * 1e-6, b3 = c.b3_fs3_per_mm[x] * 1e-9;
+        d.disp[x][0] = -c.db1_ps_per_mm[x] / T;
+        d.disp[x][1] = kPi * b2 / (T * T);
+        d.disp[x][2] = -kTwoPi * kTwoPi * b3 / (6.0 * T * T * T);
+        d.alpha_half[x] = 0.5 * c.alpha_per_mm[x];
+    }
+    d.dk_rev = c.dk_per_mm / kTwoPi;
+    // Kerr term: gamma_x = (2 pi/lambda_x) n2 (n_x eps0 c/2), per mm
+    d.kerr = c.n2_m2_per_w != 0.0;
+    for (int x = 0; x < 3; ++x)
+        d.gamma[x] = kTwoPi / (f.lambda_um[x] * 1e-6) * c.n2_m2_per_w *
+                     (0.5 * f.n[x] * 8.8541878128e-12 * 299792458.0) * 1e-3;
+}
+
+static int validate(int n, int K, const opo_fields_t *f, const opo_crystal_t *c, const opo_cavity_t *k,
                     int precision)
 {
     const int max_log2 = precision == OPO_F64 ? 19 : 20;
@@ -248,15 +274,18 @@ static int validate(int n, const opo_fields_t *f, const opo_crystal_t *c, const 
             return fail(OPO_EINVAL, at + "pump_cw must be finite");
         if (f[i].pump_windows < 0 || (f[i].pump_windows > 1 && !f[i].pump_in))
             return fail(OPO_EINVAL, at + "pump_windows must be >= 0, and > 1 only with pump_in");
-        if (!(c[i].length_mm > 0.0) || !std::isfinite(c[i].length_mm))
-            return fail(OPO_EINVAL, at + "length_mm must be finite and > 0");
-        if (c[i].nz < 1) return fail(OPO_EINVAL, at + "nz must be >= 1");
-        if (c[i].nz != c[0].nz) return fail(OPO_EINVAL, at + "all instances must share nz");
-        if (!std::isfinite(c[i].deff_pm_per_v) || !std::isfinite(c[i].dk_per_mm) ||
-            !std::isfinite(c[i].n2_m2_per_w) ||
-            !finite3(c[i].alpha_per_mm) || !finite3(c[i].db1_ps_per_mm) ||
-            !finite3(c[i].b2_fs2_per_mm) || !finite3(c[i].b3_fs3_per_mm))
-            return fail(OPO_EINVAL, at + "crystal coefficients must be finite");
+        for (int st = 0; st < K; ++st) {
+            const opo_crystal_t &cr = c[i * K + st];
+            const std::string cat = K > 1 ? at + "crystal " + std::to_string(st) + ": " : at;
+            if (!(cr.length_mm > 0.0) || !std::isfinite(cr.length_mm))
+                return fail(OPO_EINVAL, cat + "length_mm must be finite and > 0");
+            if (cr.nz < 1) return fail(OPO_EINVAL, cat + "nz must be >= 1");
+            if (cr.nz != c[st].nz) return fail(OPO_EINVAL, cat + "all instances must share nz");
+            if (!std::isfinite(cr.deff_pm_per_v) || !std::isfinite(cr.dk_per_mm) || !std::isfinite(cr.n2_m2_per_w) ||
+                !finite3(cr.alpha_per_mm) || !finite3(cr.db1_ps_per_mm) || !finite3(cr.b2_fs2_per_mm) ||
+                !finite3(cr.b3_fs3_per_mm))
+                return fail(OPO_EINVAL, cat + "crystal coefficients must be finite");
+        }
         for (int x = 0; x < 3; ++x) {
             if (!(k[i].refl[x] >= 0.0 && k[i].refl[x] <= 1.0))
                 return fail(OPO_EINVAL, at + "reflectivities must lie in [0, 1]");
@@ -275,14 +304,17 @@ static int validate(int n, const opo_fields_t *f, const opo_crystal_t *c, const 
             for (long long q = 0; q < static_cast<long long>(nt) * std::max(1, f[i].pump_windows); ++q)
                 amax = std::max(amax, std::hypot(f[i].pump_in[2 * q], f[i].pump_in[2 * q + 1]));
         if (!std::isfinite(amax)) return fail(OPO_EINVAL, at + "initial fields must be finite");
-        double kap[3], kmax = 0.0;
-        coupling(f[i], c[i].deff_pm_per_v, kap);
-        for (int x = 0; x < nf; ++x)
-            kmax = std::max(kmax, std::fabs(kap[x]));
-        const double step = kmax * amax * c[i].length_mm / c[i].nz;
-        if (!(step < 0.5))
-            return fail(OPO_EINVAL, at + "step too large for the field amplitudes (kappa |A| dz = " +
-                                        std::to_string(step) + ", needs < 0.5)");
+        for (int st = 0; st < K; ++st) {
+            const opo_crystal_t &cr = c[i * K + st];
+            double kap[3], kmax = 0.0;
+            coupling(f[i], cr.deff_pm_per_v, kap);
+            for (int x = 0; x < nf; ++x)
+                kmax = std::max(kmax, std::fabs(kap[x]));
+            const double step = kmax * amax * cr.length_mm / cr.nz;
+            if (!(step < 0.5))
+                return fail(OPO_EINVAL, at + "step too large for the field amplitudes (kappa |A| dz = " +
+                                            std::to_string(step) + ", needs < 0.5)");
+        }
     }
     return OPO_OK;
 }
@@ -504,12 +536,21 @@ template <typename R> static void enqueue_roundtrip(opo_t *h)
     a.dz_arg = 0.0;
     a.zbase = 0.0;
     const int eom = h->any_eom ? A_EOM : 0;
-    if (h->any_gdd) {
-        enqueue_pass<R>(h, a, h->nz, A_REFRESH, A_ENERGY | A_FWD);
-        launch_b<R>(h, a, B_GDD);
-        launch_a<R>(h, a, A_INV | A_MIRROR | eom, 0);
-    } else {
-        enqueue_pass<R>(h, a, h->nz, A_REFRESH, A_ENERGY | A_MIRROR | eom);
+    const int K = h->n_stage;
+    // the crystals in order, each from its own entrance; the boundary after the last
+    for (int st = 0; st < K; ++st) {
+        a.inst = h->d_inst + static_cast<size_t>(st) * h->n_inst;
+        a.nz = h->stage_nz[st];
+        const int first = st == 0 ? A_REFRESH : 0;
+        if (st + 1 < K) {
+            enqueue_pass<R>(h, a, a.nz, first, 0);
+        } else if (h->any_gdd) {
+            enqueue_pass<R>(h, a, a.nz, first, A_ENERGY | A_FWD);
+            launch_b<R>(h, a, B_GDD);
+            launch_a<R>(h, a, A_INV | A_MIRROR | eom, 0);
+        } else {
+            enqueue_pass<R>(h, a, a.nz, first, A_ENERGY | A_MIRROR | eom);
+        }
     }
     prof_begin(h, OPO_K_ENERGY);
     energy_reduce<<<1, kThreads, 0, h->stream>>>(h->d_inst, h->n_inst, h->d_partial, h->d_hist,
@@ -550,7 +591,9 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     if (opt.precision != OPO_F32 && opt.precision != OPO_F64)
         return fail(OPO_EINVAL, "precision must be OPO_F32 or OPO_F64");
     if (opt.record_rt < 0) return fail(OPO_EINVAL, "record_rt must be >= 0");
-    int rc = validate(n, f, c, k, opt.precision);
+    const int K = opt.n_crystals > 1 ? opt.n_crystals : 1;
+    if (opt.n_crystals < 0) return fail(OPO_EINVAL, "n_crystals must be >= 0");
+    int rc = validate(n, K, f, c, k, opt.precision);
     if (rc) return rc;
 
     int ndev = 0;
@@ -568,6 +611,8 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     h->device = opt.device;
     h->n_inst = n;
     h->nz = c[0].nz;
+    h->n_stage = K;
+    for (int st = 0; st < K; ++st) h->stage_nz.push_back(c[st].nz);
     h->elem = opt.precision == OPO_F64 ? 16 : 8;
     h->use_graph = opt.use_graph >= 0 ? 1 : 0;
     h->profile = opt.profile != 0;
@@ -644,21 +689,12 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         h->any_eom |= eom != 0;
 
         const double T = f[i].t_window_ps;
-        d.length_mm = c[i].length_mm;
-        coupling(f[i], c[i].deff_pm_per_v, d.kappa);
+        set_crystal(d, f[i], c[i * K]);
         for (int x = 0; x < 3; ++x) {
-            // Eq. 5 phase per mm in revolutions for bin ks (w = 2 pi ks/T):
-            // (-db1 w + b2 w^2/2 - b3 w^3/6)/(2 pi)
-            const double b2 = c[i].b2_fs2_per_mm[x] * 1e-6, b3 = c[i].b3_fs3_per_mm[x] * 1e-9;
-            d.disp[x][0] = -c[i].db1_ps_per_mm[x] / T;
-            d.disp[x][1] = kPi * b2 / (T * T);
-            d.disp[x][2] = -kTwoPi * kTwoPi * b3 / (6.0 * T * T * T);
-            d.alpha_half[x] = 0.5 * c[i].alpha_per_mm[x];
             const double sr = std::sqrt(k[i].refl[x]);
             d.mirror[x][0] = sr * std::cos(k[i].delta_rad[x]);
             d.mirror[x][1] = sr * std::sin(k[i].delta_rad[x]);
         }
-        d.dk_rev = c[i].dk_per_mm / kTwoPi;
         d.gdd_rev = kPi * k[i].gdd_fs2 * 1e-6 / (T * T);   // gamma w^2/2 / (2 pi)
         d.eom_beta = k[i].eom_beta;
         d.eom_rev0 = -0.5 * T * k[i].eom_fpm_thz;             // f t_0
@@ -667,36 +703,6 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         d.pump_cw[1] = f[i].pump_cw[1];
         // a resonant pump: the input couples in through the pump mirror
         d.inject = k[i].resonant[0] ? std::sqrt(1.0 - k[i].refl[0]) : 0.0;
-        // Kerr term: gamma_x = (2 pi/lambda_x) n2 (n_x eps0 c/2), per mm
-        d.kerr = c[i].n2_m2_per_w != 0.0;
-        for (int x = 0; x < 3; ++x)
-            d.gamma[x] = kTwoPi / (f[i].lambda_um[x] * 1e-6) * c[i].n2_m2_per_w *
-                         (0.5 * f[i].n[x] * 8.8541878128e-12 * 299792458.0) * 1e-3;
-
-    }
-
-    // ---- linear-propagator tables: instances with the same grid, crystal
-    // length and dispersion share one table
-    long long disp_elems = 0;
-    for (int i = 0; i < n; ++i) {
-        InstDesc &d = h->inst[i];
-        int same = -1;
-        for (int o : h->disp_owner) {
-            const InstDesc &e = h->inst[o];
-            if (e.nt == d.nt && e.nf == d.nf && e.length_mm == d.length_mm &&
-                std::memcmp(e.disp, d.disp, sizeof(d.disp)) == 0 &&
-                std::memcmp(e.alpha_half, d.alpha_half, sizeof(d.alpha_half)) == 0) {
-                same = o;
-                break;
-            }
-        }
-        if (same >= 0) {
-            d.disp_off = h->inst[same].disp_off;
-        } else {
-            d.disp_off = disp_elems;
-            disp_elems += static_cast<long long>(d.nf) * d.nt;
-            h->disp_owner.push_back(i);
-        }
     }
 
     // ---- halves of a batch for the mixed schedule: instances are dealt to
@@ -790,6 +796,41 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         }
     }
 
+    // ---- one descriptor per (crystal, instance): the crystals of a round trip
+    // share everything but the crystal-dependent fields
+    h->inst.resize(static_cast<size_t>(K) * n);
+    for (int st = 1; st < K; ++st)
+        for (int i = 0; i < n; ++i) {
+            InstDesc &d = h->inst[static_cast<size_t>(st) * n + i];
+            d = h->inst[i];
+            set_crystal(d, f[i], c[i * K + st]);
+        }
+
+    // ---- linear-propagator tables: descriptors with the same grid, crystal
+    // length, step count and dispersion share one table
+    long long disp_elems = 0;
+    for (int q = 0; q < K * n; ++q) {
+        InstDesc &d = h->inst[q];
+        int same = -1;
+        for (int o : h->disp_owner) {
+            const InstDesc &e = h->inst[o];
+            if (e.nt == d.nt && e.nf == d.nf && e.length_mm == d.length_mm &&
+                h->stage_nz[o / n] == h->stage_nz[q / n] &&
+                std::memcmp(e.disp, d.disp, sizeof(d.disp)) == 0 &&
+                std::memcmp(e.alpha_half, d.alpha_half, sizeof(d.alpha_half)) == 0) {
+                same = o;
+                break;
+            }
+        }
+        if (same >= 0) {
+            d.disp_off = h->inst[same].disp_off;
+        } else {
+            d.disp_off = disp_elems;
+            disp_elems += static_cast<long long>(d.nf) * d.nt;
+            h->disp_owner.push_back(q);
+        }
+    }
+
     // ---- device memory
     if (opt.state) {
         if (opt.state_bytes < need)
@@ -809,7 +850,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
             return bail(fail(OPO_ENOMEM, "hipMalloc of the round-trip record failed"));
         h->record_cap = opt.record_rt;
     }
-    if (hipMalloc(reinterpret_cast<void **>(&h->d_inst), n * sizeof(InstDesc)) != hipSuccess ||
+    if (hipMalloc(reinterpret_cast<void **>(&h->d_inst), h->inst.size() * sizeof(InstDesc)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_tile_a), h->tiles_a * sizeof(int)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_tile_b), h->tiles_b * sizeof(int)) != hipSuccess ||
         hipMalloc(&h->d_tw, static_cast<size_t>(kTwEntries) * 16) != hipSuccess ||
@@ -841,7 +882,8 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
                     twim[tw_index(rs, p, k) + r - 1] = -std::sin(a);
                 }
     hipStream_t st = h->stream;
-    if (hipMemcpyAsync(h->d_inst, h->inst.data(), n * sizeof(InstDesc), hipMemcpyHostToDevice, st) != hipSuccess ||
+    if (hipMemcpyAsync(h->d_inst, h->inst.data(), h->inst.size() * sizeof(InstDesc), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
         hipMemcpyAsync(h->d_tile_a, tile_a_inst.data(), tile_a_inst.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync(h->d_tile_b, tile_b_inst.data(), tile_b_inst.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
         (h->mixed && hipMemcpyAsync(h->d_map[0], maps[0].data(), maps[0].size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess) ||
@@ -898,7 +940,7 @@ template <typename R> static int ensure_tables(opo_t *h, double mode)
     if (h->disp_mode == mode) return OPO_OK;
     for (int o : h->disp_owner) {
         const InstDesc &d = h->inst[o];
-        const double dz = mode > 0.0 ? mode : d.length_mm / h->nz;
+        const double dz = mode > 0.0 ? mode : d.length_mm / h->stage_nz[o / h->n_inst];
         const int blocks = static_cast<int>(
             std::min<long long>((static_cast<long long>(d.nf) * d.nt + kThreads - 1) / kThreads, 4096));
         disp_table<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, o, static_cast<Phasor<R> *>(h->d_disp), dz);

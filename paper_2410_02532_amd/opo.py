@@ -53,7 +53,8 @@ class OptionsT(ctypes.Structure):
                 ("stream", ctypes.c_void_p), ("state", ctypes.c_void_p),
                 ("state_bytes", ctypes.c_uint64), ("tile_a", ctypes.c_int32),
                 ("tile_b", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("profile", ctypes.c_int32), ("record_rt", ctypes.c_int32)]
+                ("profile", ctypes.c_int32), ("record_rt", ctypes.c_int32),
+                ("n_crystals", ctypes.c_int32)]
 
 
 class OpoError(RuntimeError):
@@ -113,13 +114,33 @@ def _check(code):
     return code
 
 
+def _crystal_struct(c, cr, nz):
+    c.length_mm = cr["length_mm"]
+    c.nz = int(nz)
+    c.deff_pm_per_v = cr["deff_pm_per_v"]
+    c.dk_per_mm = cr["dk_per_mm"]
+    c.alpha_per_mm = _d3(*cr["alpha_per_mm"])
+    c.db1_ps_per_mm = _d3(*cr["db1_ps_per_mm"])
+    c.b2_fs2_per_mm = _d3(*cr["b2_fs2_per_mm"])
+    c.b3_fs3_per_mm = _d3(*cr["b3_fs3_per_mm"])
+    c.n2_m2_per_w = float(cr.get("n2_m2_per_w", 0.0))
+
+
 def _structs(instances, nz):
-    """ctypes arrays for a list of instance dicts (crystal, cavity, fields, pump_in)."""
+    """ctypes arrays for a list of instance dicts (crystal, cavity, fields, pump_in).
+
+    nz is the step count of the crystal, or a list with one per crystal when the instances
+    carry "crystals" (crystals per round trip, in order; "crystal" is then the first)."""
     n = len(instances)
-    fields, crystals, cavities = (FieldsT * n)(), (CrystalT * n)(), (CavityT * n)()
+    nzs = [int(v) for v in nz] if np.ndim(nz) else [int(nz)]
+    kc = len(nzs)
+    fields, crystals, cavities = (FieldsT * n)(), (CrystalT * (n * kc))(), (CavityT * n)()
     keep = []
     for i, ins in enumerate(instances):
-        cr, cav = ins["crystal"], ins["cavity"]
+        crs = ins.get("crystals", [ins["crystal"]])
+        if len(crs) != kc:
+            raise ValueError("instance %d has %d crystals for %d step counts" % (i, len(crs), kc))
+        cr, cav = crs[0], ins["cavity"]
         f = fields[i]
         f.nt = int(cr["nt"])
         nf = int(cr.get("nf", 3))
@@ -146,16 +167,8 @@ def _structs(instances, nz):
             keep.append(pump)
             f.pump_in = pump.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             f.pump_cw = _d2(0.0, 0.0)
-        c = crystals[i]
-        c.length_mm = cr["length_mm"]
-        c.nz = int(nz)
-        c.deff_pm_per_v = cr["deff_pm_per_v"]
-        c.dk_per_mm = cr["dk_per_mm"]
-        c.alpha_per_mm = _d3(*cr["alpha_per_mm"])
-        c.db1_ps_per_mm = _d3(*cr["db1_ps_per_mm"])
-        c.b2_fs2_per_mm = _d3(*cr["b2_fs2_per_mm"])
-        c.b3_fs3_per_mm = _d3(*cr["b3_fs3_per_mm"])
-        c.n2_m2_per_w = float(cr.get("n2_m2_per_w", 0.0))
+        for st in range(kc):
+            _crystal_struct(crystals[i * kc + st], crs[st], nzs[st])
         k = cavities[i]
         k.resonant = _i3(*[int(v) for v in cav["resonant"]])
         k.refl = _d3(*cav["refl"])
@@ -175,7 +188,8 @@ class Opo:
     crystal's ``nf`` (default 3) selects three coupled waves or the two-wave degenerate
     model. pump_in of shape (windows, nt) is a long pump read one window per round trip.
     record_rt > 0 keeps the fields leaving the crystal for the first record_rt round trips
-    (read with record()).
+    (read with record()). Several crystals per round trip: each instance carries
+    "crystals" (in order) and nz is a list of step counts, one per crystal.
     The field state lives in a torch uint8 tensor on ``device``; the library
     runs on a torch stream (default priority) created for the handle.
     """
@@ -199,7 +213,8 @@ class Opo:
                        stream=ctypes.c_void_p(self._stream.cuda_stream),
                        state=ctypes.c_void_p(self._state.data_ptr()), state_bytes=nbytes,
                        tile_a=int(tile_a), tile_b=int(tile_b), use_graph=1 if use_graph else -1,
-                       profile=1 if profile else 0, record_rt=int(record_rt))
+                       profile=1 if profile else 0, record_rt=int(record_rt),
+                       n_crystals=len(nz) if np.ndim(nz) else 1)
         h = ctypes.c_void_p()
         _check(lib.opo_init_batch(ctypes.byref(h), self.n, fields, crystals, cavities,
                                   ctypes.byref(opt)))
