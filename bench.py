@@ -224,6 +224,19 @@ def main():
             d, _ = run_gpu(ws, n, 10, prec)
             var["%s_single_sro_cw_2^14" % prec] = {"value": pt_steps_per_rt(ws) * n / d,
                                                   "round_trips": n, "ms_per_step": d * 1e3 / n}
+        # the synchronously pumped OPO at its largest grid, FP32 and FP64
+        for prec in ("f32", "f64"):
+            ws = W.config("sync_pumped", nt=1 << 18, precision=prec)
+            n = 50
+            d, _ = run_gpu(ws, n, 3, prec)
+            var["%s_sync_pumped_2^18" % prec] = {"value": pt_steps_per_rt(ws) * n / d, "round_trips": n,
+                                                 "ms_per_step": d * 1e3 / n}
+        # the large doubly resonant batch: 16 x 2^20, Nz 200, GDD and EOM
+        ws = W.config("dro_large")
+        n = 10
+        d, _ = run_gpu(ws, n, 2, "f32")
+        var["f32_dro_large_16x2^20"] = {"value": pt_steps_per_rt(ws) * n / d, "round_trips": n,
+                                        "ms_per_step": d * 1e3 / n}
         # the two-wave (degenerate) model over the same size mix
         ws = W.config("degenerate_sweep")
         n = 100

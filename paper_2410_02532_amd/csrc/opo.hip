@@ -661,7 +661,8 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         d.tiles_a = (d.n1 + d.cols - 1) / d.cols;
         d.tiles_b = d.nf * ((d.n2 + d.rows - 1) / d.rows);
         // LDS of a tile: nf fields of `cols` columns, or `rows` rows
-        max_a = std::max(max_a, static_cast<size_t>(d.nf) * d.cols * d.n2);
+        const bool seq = opt.precision == OPO_F64 ? col_seq_lds<double>(p.log2n2) : col_seq_lds<float>(p.log2n2);
+        max_a = std::max(max_a, static_cast<size_t>(seq ? 1 : d.nf) * d.cols * d.n2);
         max_b = std::max(max_b, static_cast<size_t>(d.rows) * d.n1);
         // shapes the kernels are instantiated for
         const int max_ln1 = opt.precision == OPO_F64 ? kMaxLog2N1<double> : kMaxLog2N1<float>;

@@ -124,6 +124,14 @@ template <typename R> __host__ __device__ constexpr int col_cols(int ln2)
 {
     return kThreads * col_pf<R>(ln2) >> ln2;
 }
+// Column tiles whose fields would need more than 32 KB of LDS for one
+// exchange pass their fields through it one at a time (a single field's
+// worth of LDS), so that several workgroups still fit a CU.
+template <typename R> __host__ __device__ constexpr bool col_seq_lds(int ln2)
+{
+    return 3LL * col_cols<R>(ln2) * (1LL << ln2) * 2 * static_cast<long long>(sizeof(R)) > 32768;
+}
+
 // Row tile for rows of length 2^ln1: PF samples per thread, at least 16
 // threads (128 B) along a row, ROWS rows per tile.
 template <typename R> __host__ __device__ constexpr int row_pf(int ln1)
@@ -365,6 +373,29 @@ struct ColumnShared {
 };
 
 // ------------------------------------------------------------------------
+// The column FFTs of the NF fields of a tile: all fields through LDS
+// together, or one after another for the large columns (col_seq_lds).
+template <typename R, int LN2, int PF, int NF, int DIR, int COLS>
+__device__ __forceinline__ void column_fft(cplx<R> (&v)[NF][PF], cplx<R> *s, const int (&base)[NF], int t,
+                                           const Phasor<R> *__restrict__ tw)
+{
+    constexpr int N = 1 << LN2;
+    if constexpr (N > 1 && col_seq_lds<R>(LN2)) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            cplx<R> w[1][PF];
+#pragma unroll
+            for (int m = 0; m < PF; ++m) w[0][m] = v[f][m];
+            const int b1[1] = {base[0]};
+            reg_fft<R, N, PF, 1, DIR, COLS>(w, s, b1, t, tw);
+#pragma unroll
+            for (int m = 0; m < PF; ++m) v[f][m] = w[0][m];
+        }
+    } else {
+        reg_fft<R, N, PF, NF, DIR, COLS>(v, s, base, t, tw);
+    }
+}
+
 // Column pass of one tile: COLS columns j1 = c0 + c of the NF fields.
 // Thread (c, t) holds samples j2 (or k2) = t + m*T, m < PF, of column c.
 template <typename R, int LN2, int NF>
@@ -415,7 +446,7 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
                 for (int f = 0; f < NF; ++f) v[f][m] = pmul<true>(v[f][m], w);
             }
         }
-        reg_fft<R, N, PF, NF, +1, COLS>(v, s, base, t, a.tw);
+        column_fft<R, LN2, PF, NF, +1, COLS>(v, s, base, t, a.tw);
     }
     if (flags & (A_RK_PREV | A_RK_THIS)) __syncthreads();   // couplings visible
 
@@ -482,7 +513,7 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     }
 
     if (flags & A_FWD) {
-        reg_fft<R, N, PF, NF, -1, COLS>(v, s, base, t, a.tw);
+        column_fft<R, LN2, PF, NF, -1, COLS>(v, s, base, t, a.tw);
         if constexpr (N > 1) {
 #pragma unroll
             for (int m = 0; m < PF; ++m) {
