@@ -109,12 +109,15 @@ template <typename R> struct StepArgs {
 
 // ---------------------------------------------------------------- shapes --
 // Column tile for columns of length 2^ln2: PF samples per thread and field,
-// COLS columns so that COLS * sizeof(complex) = 128 B (one cache line).
+// COLS columns so that COLS * sizeof(complex) = 128 B (one cache line), and
+// at most 8 samples per thread and field (the 256-point FP32 columns then
+// take 8 columns, 64 B: 16 samples of three fields held the registers of
+// two waves per SIMD and ran at half the speed).
 template <typename R> __host__ __device__ constexpr int col_pf(int ln2)
 {
     const int n = 1 << ln2;
     const int cmin = 128 / (2 * static_cast<int>(sizeof(R)));
-    const int pfmax = sizeof(R) == 4 ? 16 : 8;
+    const int pfmax = 8;
     if (n == 1) return 1;
     int pf = cmin * n / kThreads;
     pf = pf < 2 ? 2 : pf;
