@@ -708,9 +708,10 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
 
     // ---- halves of a batch for the mixed schedule: instances are dealt to
     // two halves of similar size (largest first); the schedule is used when
-    // each half then has one column and one row size range and no GDD pass
+    // each half then has one column and one row size range (a GDD row pass
+    // and the column pass after it run over both halves at the round-trip end)
     std::vector<int> half(n, 0);
-    if (n >= 2 && !h->any_gdd) {
+    if (n >= 2) {
         std::vector<int> order(n);
         for (int i = 0; i < n; ++i) order[i] = i;
         std::stable_sort(order.begin(), order.end(),
@@ -752,7 +753,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         }
     if (static_cast<int>(tile_a_inst.size()) != h->tiles_a || static_cast<int>(tile_b_inst.size()) != h->tiles_b)
         return bail(fail(OPO_EINVAL, "internal: a transform length has no kernel"));
-    if (n >= 2 && !h->any_gdd && h->groups_a.size() == 2 && h->groups_b.size() == 2 &&
+    if (n >= 2 && h->groups_a.size() == 2 && h->groups_b.size() == 2 &&
         h->groups_a[0].half == 0 && h->groups_a[1].half == 1 && h->groups_b[0].half == 0 &&
         h->groups_b[1].half == 1) {
         const bool f64 = opt.precision == OPO_F64;

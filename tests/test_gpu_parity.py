@@ -246,3 +246,31 @@ def test_mixed_schedule_batch_equals_singles_and_oracle():
         for x in range(3):
             assert rel_l2(batch[i][0][x], ref[x]) <= 10 * TOL["f32"], (i, x)
             assert np.max(np.abs(batch[i][1][:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E["f32"]
+
+
+def test_mixed_schedule_with_gdd_and_eom():
+    """A batch on the mixed schedule whose cavities carry chirped-mirror GDD (on the signal
+    only for one instance) and an EOM: the GDD row pass and the column pass after it cover
+    both halves; every instance equals its own single run bit for bit, and the oracle."""
+    say("mixed schedule + GDD")
+    sizes = [4096, 8192, 4096, 8192]
+    insts = []
+    for b, nt in enumerate(sizes):
+        ins = _stress(nt, seed=70 + b)
+        ins["cavity"] = W.cavity(resonant=(0, 1, 1), refl=(0.0, 0.9, 0.85), delta=(0.0, 0.1 * b, -0.2),
+                                 gdd_fs2=-800.0 + 500.0 * b, gdd_on=(0, 1, 0) if b == 2 else None,
+                                 eom_beta=0.4, eom_fpm_thz=1.0 / 40.0)
+        insts.append(ins)
+    nz, nrt = 6, 3
+    with B.Opo(insts, nz, precision="f32") as hb:
+        hb.cavity_roundtrip(nrt)
+        batch = [(hb.get_fields(i), hb.energy_history(i)) for i in range(len(sizes))]
+    for i, ins in enumerate(insts):
+        with _handle(ins, nz, "f32") as h:
+            h.cavity_roundtrip(nrt)
+            assert np.array_equal(batch[i][0], h.get_fields())
+            assert np.array_equal(batch[i][1], h.energy_history())
+        ref, e_ref = oracle.roundtrips(ins["crystal"], ins["cavity"], ins["fields"], ins["pump_in"], nz, nrt)
+        for x in range(3):
+            assert rel_l2(batch[i][0][x], ref[x]) <= 10 * TOL["f32"], (i, x)
+            assert np.max(np.abs(batch[i][1][:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E["f32"]
