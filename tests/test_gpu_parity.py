@@ -58,8 +58,9 @@ def _handle(inst, nz, precision, **kw):
     return B.Opo([inst], nz, precision=precision, **kw)
 
 
-@pytest.mark.parametrize("precision", ["f64", "f32"])
-@pytest.mark.parametrize("nt", [2, 4, 8, 64, 512, 1 << 12, 1 << 14, 1 << 16])
+@pytest.mark.parametrize("precision, nt", [(p, n) for p in ("f64", "f32")
+                                           for n in (2, 4, 8, 64, 512, 1 << 12, 1 << 14, 1 << 16)]
+                         + [("f64", 1 << 19), ("f32", 1 << 20)])   # the largest grids
 def test_pass_parity(nt, precision):
     say("pass parity nt=%d %s" % (nt, precision))
     ins = _stress(nt, seed=nt)
@@ -69,9 +70,15 @@ def test_pass_parity(nt, precision):
         h.ssfm_propagate(nz, dz)
         got = h.get_fields()
         assert h.info()[1] == pytest.approx(nz * dz)
+    tol = TOL[precision]
+    if precision == "f64" and nt > 1 << 16:
+        # third-order dispersion at the Nyquist edge of the 2^19 grid on the 40 ps window:
+        # b3 w_N^3 / 6 dz ~ 9e5 rad per step, whose FP64 argument carries ~1e-10 rad of
+        # rounding that the two sides round differently (the bar scales with that phase)
+        tol = 1e-10
     for x in range(3):
-        assert rel_l2(got[x], ref[x]) <= TOL[precision], (x, rel_l2(got[x], ref[x]))
-        assert rel_max(got[x], ref[x]) <= 10 * TOL[precision]
+        assert rel_l2(got[x], ref[x]) <= tol, (x, rel_l2(got[x], ref[x]))
+        assert rel_max(got[x], ref[x]) <= 10 * tol
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
