@@ -34,13 +34,16 @@ constexpr int kTwL = 8192;      // longest transform the twiddle table serves
 __host__ __device__ constexpr int tw_block_size(int rs) { return (2 * (kTwL / rs) - 1) * (rs - 1); }
 __host__ __device__ constexpr int tw_block(int rs)
 {
-    return rs == 2 ? 0 : rs == 4 ? tw_block_size(2) : tw_block_size(2) + tw_block_size(4);
+    return rs == 2    ? 0
+           : rs == 4  ? tw_block_size(2)
+           : rs == 8  ? tw_block_size(2) + tw_block_size(4)
+                      : tw_block_size(2) + tw_block_size(4) + tw_block_size(8);
 }
 __host__ __device__ constexpr int tw_index(int rs, int p, int k)
 {
     return tw_block(rs) + (p - 1 + k) * (rs - 1);
 }
-constexpr int kTwEntries = tw_block_size(2) + tw_block_size(4) + tw_block_size(8);
+constexpr int kTwEntries = tw_block_size(2) + tw_block_size(4) + tw_block_size(8) + tw_block_size(16);
 
 template <typename R> struct cplx_of;
 template <> struct cplx_of<float> { using type = float2; };
@@ -192,17 +195,61 @@ template <int DIR, typename V> __device__ __forceinline__ void dft8(V *x)
     x[7] = csub(e[3], o3);
 }
 
+// 16 points as 4 x 4: DFT4 over the samples j1 + 4 j2 of each j1, the
+// internal twiddles w^{j1 k1} (w = e^{DIR 2 pi i/16}), then DFT4 over j1;
+// output k1 + 4 k2. w^2, w^4 and w^6 take the eighth-root products of dft8;
+// w, w^3 and w^9 = -w are compensated FP32 phasors like every other
+// unit-modulus factor.
+template <int DIR, typename V> __device__ __forceinline__ void dft16(V *x)
+{
+    using R = decltype(x[0].x);
+    constexpr double c8 = 0.92387953251128675613, s8 = 0.38268343236508977173;   // cos, sin of pi/8
+    const Phasor<R> w1 = make_phasor<R>(c8, DIR * s8);
+    const Phasor<R> w3 = make_phasor<R>(s8, DIR * c8);
+    V a[4][4];
+#pragma unroll
+    for (int j1 = 0; j1 < 4; ++j1) {
+#pragma unroll
+        for (int j2 = 0; j2 < 4; ++j2) a[j1][j2] = x[j1 + 4 * j2];
+        dft4<DIR>(a[j1]);
+    }
+    // a[j1][k1] *= w^{j1 k1}
+    a[1][1] = pmul(a[1][1], w1);
+    a[1][2] = mk<V>(mul_rsqrt2(a[1][2].x - DIR * a[1][2].y), mul_rsqrt2(a[1][2].y + DIR * a[1][2].x));
+    a[1][3] = pmul(a[1][3], w3);
+    a[2][1] = mk<V>(mul_rsqrt2(a[2][1].x - DIR * a[2][1].y), mul_rsqrt2(a[2][1].y + DIR * a[2][1].x));
+    a[2][2] = rot90<DIR>(a[2][2]);
+    a[2][3] = mk<V>(mul_rsqrt2(-a[2][3].x - DIR * a[2][3].y), mul_rsqrt2(-a[2][3].y + DIR * a[2][3].x));
+    a[3][1] = pmul(a[3][1], w3);
+    a[3][2] = mk<V>(mul_rsqrt2(-a[3][2].x - DIR * a[3][2].y), mul_rsqrt2(-a[3][2].y + DIR * a[3][2].x));
+    a[3][3] = pmul(a[3][3], w1);
+    a[3][3] = mk<V>(-a[3][3].x, -a[3][3].y);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        V b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+        dft4<DIR>(b);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) x[k1 + 4 * k2] = b[k2];
+    }
+}
+
 template <int RAD, int DIR, typename V> __device__ __forceinline__ void dft(V *x)
 {
-    if constexpr (RAD == 8) dft8<DIR>(x);
+    if constexpr (RAD == 16) dft16<DIR>(x);
+    else if constexpr (RAD == 8) dft8<DIR>(x);
     else if constexpr (RAD == 4) dft4<DIR>(x);
     else dft2<DIR>(x);
 }
 
 // Radix of the stage that follows sub-transforms of length P.
+// Radix 16 serves transforms of up to 2048 points (at 4096 four radix-8
+// stages ran faster than three radix-16 ones).
 template <int N, int PF, int P> __host__ __device__ constexpr int stage_radix()
 {
-    return (N / P >= 8 && PF % 8 == 0) ? 8 : (N / P >= 4 && PF % 4 == 0) ? 4 : 2;
+    return (N <= 2048 && N / P >= 16 && PF % 16 == 0) ? 16
+           : (N / P >= 8 && PF % 8 == 0) ? 8
+           : (N / P >= 4 && PF % 4 == 0) ? 4
+                                          : 2;
 }
 
 // One stage over NTR transforms held by this thread. Position n of transform

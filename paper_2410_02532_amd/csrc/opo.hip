@@ -875,7 +875,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
 
     // stage-major butterfly twiddles (fft_tile.h, tw_index)
     std::vector<double> twre(kTwEntries, 1.0), twim(kTwEntries, 0.0);
-    for (int rs : {2, 4, 8})
+    for (int rs : {2, 4, 8, 16})
         for (int p = 1; p * rs <= kTwL; p *= 2)
             for (int k = 0; k < p; ++k)
                 for (int r = 1; r < rs; ++r) {

@@ -136,14 +136,18 @@ template <typename R> __host__ __device__ constexpr bool col_seq_lds(int ln2)
 }
 
 // Row tile for rows of length 2^ln1: PF samples per thread, at least 16
-// threads (128 B) along a row, ROWS rows per tile.
+// threads (128 B) along a row, ROWS rows per tile. FP32 rows of 256 points
+// and more (but 512) take 16 samples, for radix-16 stages: one stage and one
+// LDS exchange fewer than radix 8 (512 = 8 x 8 x 8 gains nothing from it);
+// in FP64 the registers are better spent on occupancy.
 template <typename R> __host__ __device__ constexpr int row_pf(int ln1)
 {
     const int n = 1 << ln1;
     if (n == 1) return 1;
+    if (sizeof(R) == 4 && n >= 256 && n != 512) return n / 16 > kThreads ? n / kThreads : 16;
     int pf = n / 16;
     pf = pf < 2 ? 2 : pf;
-    pf = pf > 8 ? 8 : pf;                        // radix-8 stages need no more
+    pf = pf > 8 ? 8 : pf;
     return n / pf > kThreads ? n / kThreads : pf;  // at most one row per workgroup
 }
 template <typename R> __host__ __device__ constexpr int row_rows(int ln1)
