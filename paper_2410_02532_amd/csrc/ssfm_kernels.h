@@ -136,15 +136,17 @@ template <typename R> __host__ __device__ constexpr bool col_seq_lds(int ln2)
 }
 
 // Row tile for rows of length 2^ln1: PF samples per thread, at least 16
-// threads (128 B) along a row, ROWS rows per tile. FP32 rows of 256 points
-// and more (but 512) take 16 samples, for radix-16 stages: one stage and one
-// LDS exchange fewer than radix 8 (512 = 8 x 8 x 8 gains nothing from it);
-// in FP64 the registers are better spent on occupancy.
+// threads (128 B) along a row, ROWS rows per tile. FP32 rows of 1024 points
+// and more take 16 samples, for radix-16 stages: one stage and one LDS
+// exchange fewer than radix 8. (At 256 points the tiles of four times the
+// rows halve the workgroups of a single instance, whose launches are then
+// too few to fill the chip; in FP64 the registers are better spent on
+// occupancy.)
 template <typename R> __host__ __device__ constexpr int row_pf(int ln1)
 {
     const int n = 1 << ln1;
     if (n == 1) return 1;
-    if (sizeof(R) == 4 && n >= 256 && n != 512) return n / 16 > kThreads ? n / kThreads : 16;
+    if (sizeof(R) == 4 && n >= 1024) return n / 16 > kThreads ? n / kThreads : 16;
     int pf = n / 16;
     pf = pf < 2 ? 2 : pf;
     pf = pf > 8 ? 8 : pf;
