@@ -43,6 +43,11 @@
  *     pump and non-resonant signal/idler start at zero; after the pass the
  *     energies sum_j |A_x(t_j)|^2 are recorded, then GDD, then
  *     sqrt(R_x) e^{i delta_x} on resonant fields, then the EOM phase.
+ *   - Fourth-order splitting (crystal order = 4; the paper keeps the
+ *     second-order symmetrized step and points to the literature for
+ *     higher orders): every step of size dz is the composition of three
+ *     symmetrized steps of a dz, b dz, a dz, a = 1/(2 - 2^(1/3)), b = 1 - 2a
+ *     (the Yoshida / Suzuki triple jump), each with its own z range.
  *   - Several crystals per round trip (an extension the paper names): the
  *     fields pass them in order, each crystal with its own parameters, step
  *     count and z measured from its own entrance (so its e^{i dk z} starts at
@@ -98,6 +103,7 @@ typedef struct {
     double b2_fs2_per_mm[3];
     double b3_fs3_per_mm[3];
     double n2_m2_per_w;    /* Kerr (chi(3)) nonlinear index, 0 = none       */
+    int order;             /* splitting order: 2 (symmetrized) or 4         */
 } ora_crystal;
 
 typedef struct {
@@ -311,22 +317,49 @@ void ora_linear(const ora_crystal *c, cplx *a, double dz)
 
 /* ---------------------------------------------------------- SSFM -- */
 
-/* nz symmetrized steps (Eqs. 10-11): N(dz/2) -> F^-1 e^{L dz} F -> N(dz/2),
- * step j starting at z0 + j dz. */
+/* One symmetrized step of size tau from z (Eqs. 10-11): N(tau/2) ->
+ * F^-1 e^{L tau} F -> N(tau/2), with the propagators h of that step. */
+static void strang_step(const ora_crystal *c, cplx *a, double z, double tau, const cplx *h,
+                        const cplx *w)
+{
+    int n = c->nt;
+    ora_rk4(c, a, z, 0.5 * tau);
+    for (int x = 0; x < c->nf; x++)
+        linear_with(a + (size_t)x * n, n, h + (size_t)x * n, w);
+    ora_rk4(c, a, z + 0.5 * tau, 0.5 * tau);
+}
+
+/* Fourth-order composition of symmetrized steps (the higher-order splitting
+ * the paper points to for users who need it): S(a dz) S(b dz) S(a dz) with
+ * a = 1/(2 - 2^(1/3)), b = 1 - 2a; the middle step runs backwards. */
+#define ORA_TJ_A 1.35120719195965763405
+#define ORA_TJ_B (-1.70241438391931526810)
+
+/* nz steps of size dz, step j starting at z0 + j dz: symmetrized (order 2)
+ * or the fourth-order composition (order 4). */
 void ora_pass(const ora_crystal *c, cplx *a, int nz, double dz, double z0)
 {
     int n = c->nt;
     cplx *w = twiddles(n);
     cplx *h = malloc(sizeof(cplx) * (size_t)n * 3);
-    for (int x = 0; x < c->nf; x++)
-        ora_dispersion(c, x, dz, h + (size_t)x * n);
+    cplx *hb = malloc(sizeof(cplx) * (size_t)n * 3);
+    int four = c->order == 4;
+    for (int x = 0; x < c->nf; x++) {
+        ora_dispersion(c, x, four ? ORA_TJ_A * dz : dz, h + (size_t)x * n);
+        if (four)
+            ora_dispersion(c, x, ORA_TJ_B * dz, hb + (size_t)x * n);
+    }
     for (int j = 0; j < nz; j++) {
         double zj = z0 + (double)j * dz;
-        ora_rk4(c, a, zj, 0.5 * dz);
-        for (int x = 0; x < c->nf; x++)
-            linear_with(a + (size_t)x * n, n, h + (size_t)x * n, w);
-        ora_rk4(c, a, zj + 0.5 * dz, 0.5 * dz);
+        if (!four) {
+            strang_step(c, a, zj, dz, h, w);
+        } else {
+            strang_step(c, a, zj, ORA_TJ_A * dz, h, w);
+            strang_step(c, a, zj + ORA_TJ_A * dz, ORA_TJ_B * dz, hb, w);
+            strang_step(c, a, zj + (ORA_TJ_A + ORA_TJ_B) * dz, ORA_TJ_A * dz, h, w);
+        }
     }
+    free(hb);
     free(h);
     free(w);
 }

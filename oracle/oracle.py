@@ -35,13 +35,15 @@ class Crystal(ctypes.Structure):
         ("b2_fs2_per_mm", _c3),
         ("b3_fs3_per_mm", _c3),
         ("n2_m2_per_w", ctypes.c_double),
+        ("order", ctypes.c_int),
     ]
 
     @classmethod
     def from_dict(cls, d):
         c = cls()
         for name, ctype in cls._fields_:
-            v = d.get(name, 3) if name == "nf" else d.get(name, 0.0) if name == "n2_m2_per_w" else d[name]
+            defaults = {"nf": 3, "n2_m2_per_w": 0.0, "order": 2}
+            v = d.get(name, defaults[name]) if name in defaults else d[name]
             if ctype in (_c3,):
                 setattr(c, name, _c3(*[float(x) for x in v]))
             elif ctype is ctypes.c_int:
