@@ -150,6 +150,12 @@ typedef struct {
                                with its own nz (shared by the instances) and z
                                from its own entrance, and the boundary follows
                                the last; ssfm_propagate uses crystal 0            */
+    int32_t split_order;    /* 2 (or 0): the symmetrized step of Eqs. 10-11;
+                               4: fourth-order composition of symmetrized steps
+                               of a dz, b dz, a dz, a = 1/(2 - 2^(1/3)), b = 1 - 2a
+                               (the higher-order splitting the paper leaves to
+                               the user; three times the work per step, the step
+                               criterion applies to |b| dz)                       */
 } opo_options_t;
 
 /* Device bytes of field state for n instances (n_fields * nt complex values

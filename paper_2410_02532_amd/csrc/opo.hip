@@ -149,6 +149,7 @@ struct opo_s {
     int n_inst = 0;
     int nz = 1;                      // steps of the first crystal
     int n_stage = 1;                 // crystals per round trip
+    int order = 2;                   // splitting order: 2 symmetrized, 4 triple jump
     std::vector<int> stage_nz;       // steps per pass of each crystal
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -210,6 +211,11 @@ static bool finite3(const double *v)
     return std::isfinite(v[0]) && std::isfinite(v[1]) && std::isfinite(v[2]);
 }
 
+// Triple-jump coefficients of the fourth-order composition: a = 1/(2 - 2^(1/3)),
+// b = 1 - 2a (a + b + a = 1, 2a^3 + b^3 = 0).
+constexpr double kTjA = 1.35120719195965763405;
+constexpr double kTjB = -1.70241438391931526810;
+
 // Coupled waves of an instance: 3 (pump, signal, idler; n_fields 0 or 3) or 2
 // (pump and degenerate signal).
 static int nfields(const opo_fields_t &f) { return f.n_fields == 2 ? 2 : 3; }
@@ -252,7 +258,7 @@ static void set_crystal(InstDesc &d, const opo_fields_t &f, const opo_crystal_t 
 }
 
 static int validate(int n, int K, const opo_fields_t *f, const opo_crystal_t *c, const opo_cavity_t *k,
-                    int precision)
+                    int precision, double step_scale)
 {
     const int max_log2 = precision == OPO_F64 ? 19 : 20;
     for (int i = 0; i < n; ++i) {
@@ -310,7 +316,7 @@ static int validate(int n, int K, const opo_fields_t *f, const opo_crystal_t *c,
             coupling(f[i], cr.deff_pm_per_v, kap);
             for (int x = 0; x < nf; ++x)
                 kmax = std::max(kmax, std::fabs(kap[x]));
-            const double step = kmax * amax * cr.length_mm / cr.nz;
+            const double step = kmax * amax * step_scale * cr.length_mm / cr.nz;
             if (!(step < 0.5))
                 return fail(OPO_EINVAL, at + "step too large for the field amplitudes (kappa |A| dz = " +
                                             std::to_string(step) + ", needs < 0.5)");
@@ -414,6 +420,21 @@ template <typename R> static StepArgs<R> base_args(opo_t *h, void *state)
     return a;
 }
 
+static void substep(const opo_t *h, int i, double &z, double &tau, int &sel)
+{
+    if (h->order != 4) {
+        z = i;
+        tau = 1.0;
+        sel = 0;
+        return;
+    }
+    const int j = i >= 0 ? i / 3 : -1, s = i - 3 * j;
+    const double start[3] = {0.0, kTjA, kTjA + kTjB}, size[3] = {kTjA, kTjB, kTjA};
+    z = j + start[s];
+    tau = size[s];
+    sel = s == 1 ? 1 : 0;
+}
+
 // profile option: open an event pair around the next launch of class k
 static void prof_begin(opo_t *h, int k)
 {
@@ -452,11 +473,30 @@ static int prof_collect(opo_t *h, size_t used)
     return OPO_OK;
 }
 
+// Step i of a pass in units of dz: start z, size tau, and the propagator
+// table it uses. Symmetrized steps are the steps; the fourth-order
+// composition runs three per step, of a, b and a times dz.
+static void substep(const opo_t *h, int i, double &z, double &tau, int &sel);
+
+// The RK4 half-steps a column launch at step boundary i runs: the second
+// half of step i-1 and the first half of step i.
+template <typename R> static void set_half_steps(const opo_t *h, StepArgs<R> &a, int i)
+{
+    double z, tau;
+    int sel;
+    substep(h, i - 1, z, tau, sel);
+    a.zf_prev = z + 0.5 * tau;
+    a.hf_prev = 0.5 * tau;
+    substep(h, i, z, tau, sel);
+    a.zf_this = z;
+    a.hf_this = 0.5 * tau;
+}
+
 template <typename R> static void launch_a(opo_t *h, StepArgs<R> a, int flags, int step, int half = -1)
 {
     a.tile_inst = h->d_tile_a;
     a.flags = flags;
-    a.step = step;
+    set_half_steps<R>(h, a, step);
     prof_begin(h, OPO_K_COLUMN);
     for (const Group &g : h->groups_a) {
         if (half >= 0 && g.half != half) continue;
@@ -468,10 +508,12 @@ template <typename R> static void launch_a(opo_t *h, StepArgs<R> a, int flags, i
     prof_end(h);
 }
 
-template <typename R> static void launch_b(opo_t *h, StepArgs<R> a, int flags)
+template <typename R> static void launch_b(opo_t *h, StepArgs<R> a, int flags, int step = 0)
 {
     a.tile_inst = h->d_tile_b;
     a.flags = flags;
+    double z, tau;
+    substep(h, step, z, tau, a.disp_sel);
     prof_begin(h, OPO_K_ROW);
     for (const Group &g : h->groups_b) {
         a.tile0 = g.tile0;
@@ -490,12 +532,17 @@ template <typename R> static void launch_mixed(opo_t *h, StepArgs<R> a, int ch, 
     StepArgs<R> ac = a, ar = a;
     ac.tile_inst = h->d_tile_a;
     ac.flags = cflags;
-    ac.step = step;
+    set_half_steps<R>(h, ac, step);
     ac.tile0 = gc.tile0;
     ac.tile_count = gc.count;
     ac.block_map = h->d_map[ch];
     ar.tile_inst = h->d_tile_b;
     ar.flags = B_DISP;
+    {
+        // the other half is a launch ahead (half 0) or behind (half 1)
+        double z, tau;
+        substep(h, ch == 1 ? step : step - 1, z, tau, ar.disp_sel);
+    }
     ar.tile0 = gr.tile0;
     ar.tile_count = gr.count;
     void *args[] = {&ac, &ar};
@@ -508,8 +555,9 @@ template <typename R> static void launch_mixed(opo_t *h, StepArgs<R> a, int ch, 
 // One crystal pass of nz steps. `first` flags are OR-ed into the opening
 // column pass (refresh), `last` into the closing one (energy, mirror, EOM).
 template <typename R>
-static void enqueue_pass(opo_t *h, StepArgs<R> a, int nz, int first, int last)
+static void enqueue_pass(opo_t *h, StepArgs<R> a, int nz_steps, int first, int last)
 {
+    const int nz = nz_steps * (h->order == 4 ? 3 : 1);   // symmetrized steps of the pass
     if (h->mixed) {
         // half 0 runs one launch ahead of half 1
         const int mid = A_INV | A_RK_PREV | A_RK_THIS | A_FWD;
@@ -523,7 +571,7 @@ static void enqueue_pass(opo_t *h, StepArgs<R> a, int nz, int first, int last)
     }
     launch_a<R>(h, a, first | A_RK_THIS | A_FWD, 0);
     for (int j = 0; j < nz; ++j) {
-        launch_b<R>(h, a, B_DISP);
+        launch_b<R>(h, a, B_DISP, j);
         if (j + 1 < nz) launch_a<R>(h, a, A_INV | A_RK_PREV | A_RK_THIS | A_FWD, j + 1);
         else launch_a<R>(h, a, A_INV | A_RK_PREV | last, nz);
     }
@@ -593,7 +641,10 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     if (opt.record_rt < 0) return fail(OPO_EINVAL, "record_rt must be >= 0");
     const int K = opt.n_crystals > 1 ? opt.n_crystals : 1;
     if (opt.n_crystals < 0) return fail(OPO_EINVAL, "n_crystals must be >= 0");
-    int rc = validate(n, K, f, c, k, opt.precision);
+    if (opt.split_order != 0 && opt.split_order != 2 && opt.split_order != 4)
+        return fail(OPO_EINVAL, "split_order must be 2, 4 or 0 (= 2)");
+    // the longest symmetrized step of the fourth-order composition is |b| dz
+    int rc = validate(n, K, f, c, k, opt.precision, opt.split_order == 4 ? -kTjB : 1.0);
     if (rc) return rc;
 
     int ndev = 0;
@@ -612,6 +663,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     h->n_inst = n;
     h->nz = c[0].nz;
     h->n_stage = K;
+    h->order = opt.split_order == 4 ? 4 : 2;
     for (int st = 0; st < K; ++st) h->stage_nz.push_back(c[st].nz);
     h->elem = opt.precision == OPO_F64 ? 16 : 8;
     h->use_graph = opt.use_graph >= 0 ? 1 : 0;
@@ -828,7 +880,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
             d.disp_off = h->inst[same].disp_off;
         } else {
             d.disp_off = disp_elems;
-            disp_elems += static_cast<long long>(d.nf) * d.nt;
+            disp_elems += static_cast<long long>(d.nf) * d.nt * (h->order == 4 ? 2 : 1);
             h->disp_owner.push_back(q);
         }
     }
@@ -945,7 +997,16 @@ template <typename R> static int ensure_tables(opo_t *h, double mode)
         const double dz = mode > 0.0 ? mode : d.length_mm / h->stage_nz[o / h->n_inst];
         const int blocks = static_cast<int>(
             std::min<long long>((static_cast<long long>(d.nf) * d.nt + kThreads - 1) / kThreads, 4096));
-        disp_table<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, o, static_cast<Phasor<R> *>(h->d_disp), dz);
+        if (h->order == 4) {
+            // propagators of the a dz and b dz steps of the composition
+            disp_table<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, o, static_cast<Phasor<R> *>(h->d_disp),
+                                                              kTjA * dz, 0);
+            disp_table<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, o, static_cast<Phasor<R> *>(h->d_disp),
+                                                              kTjB * dz, 1);
+        } else {
+            disp_table<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, o, static_cast<Phasor<R> *>(h->d_disp),
+                                                              dz, 0);
+        }
     }
     HIP_TRY(hipGetLastError());
     h->disp_mode = mode;

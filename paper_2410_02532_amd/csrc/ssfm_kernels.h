@@ -101,10 +101,14 @@ template <typename R> struct StepArgs {
     int tile_count;           // tiles of this launch
     const int *block_map;     // mixed launches: workgroup -> tile (see mixed_pass)
     int flags;
-    int step;                 // z-step j whose first half-step this launch runs
     int nz;                   // steps per pass (dz = L/nz when dz_arg <= 0)
+    int disp_sel;             // row pass: propagator table of this step size (0 or 1)
     double dz_arg;            // explicit step, or <= 0
     double zbase;             // z of step 0
+    // RK4 half-steps of a column launch, in units of the instance's dz: the
+    // second half of the previous step starts at zf_prev with size hf_prev,
+    // the first half of this step at zf_this with size hf_this (z from zbase)
+    double zf_prev, hf_prev, zf_this, hf_this;
 };
 
 // ---------------------------------------------------------------- shapes --
@@ -183,29 +187,30 @@ __device__ __forceinline__ Phasor<R> twiddle4(const double2 *__restrict__ t, int
 // e^{+i dk z}, i kappa_i e^{+i dk z}) * h/2 at z0, z0 + h/2, z0 + h.
 template <typename R> struct Coupling {
     cplx<R> c[2][3][3];   // [previous / this half-step][stage position][field]
-    R g[3];               // Kerr coefficients gamma_x h/2
+    R g[2][3];            // Kerr coefficients gamma_x h/2 [previous / this half-step]
 };
 
 // Computed by six threads in FP64 and shared through LDS.
 template <typename R>
-__device__ __forceinline__ void coupling_tile(const InstDesc &d, double z_prev, double z_this,
-                                              double dz, Coupling<R> *out)
+__device__ __forceinline__ void coupling_tile(const InstDesc &d, double z_prev, double h_prev, double z_this,
+                                              double h_this, Coupling<R> *out)
 {
     using V = cplx<R>;
     const int q = threadIdx.x;
     if (q < 6) {
         const int which = q / 3, st = q - 3 * which;
-        const double z = (which ? z_this : z_prev) + 0.25 * dz * st;
+        const double h = which ? h_this : h_prev;
+        const double z = (which ? z_this : z_prev) + 0.5 * h * st;
         const double r = d.dk_rev * z;
         double sn, cs;
         sincospi(2.0 * (r - rint(r)), &sn, &cs);
-        const double hh = 0.25 * dz;
+        const double hh = 0.5 * h;
         const double kp = d.kappa[0] * hh, ks = d.kappa[1] * hh, ki = d.kappa[2] * hh;
         // i kappa e^{-i th} = kappa (sin th + i cos th); i kappa e^{+i th} = kappa (-sin th + i cos th)
         out->c[which][st][0] = mk<V>(static_cast<R>(kp * sn), static_cast<R>(kp * cs));
         out->c[which][st][1] = mk<V>(static_cast<R>(-ks * sn), static_cast<R>(ks * cs));
         out->c[which][st][2] = mk<V>(static_cast<R>(-ki * sn), static_cast<R>(ki * cs));
-        if (q < 3) out->g[q] = static_cast<R>(d.gamma[q] * hh);
+        out->g[which][st] = static_cast<R>(d.gamma[st] * hh);   // st doubles as the field index
     }
 }
 
@@ -340,7 +345,7 @@ __device__ __forceinline__ void rk4_fields(const Coupling<R> &cp, int which, boo
 {
     const cplx<R>(&c)[3][3] = cp.c[which];
     if (kerr) {
-        rk4_kerr<R, NF>(c, cp.g, y0, y1, y2);
+        rk4_kerr<R, NF>(c, cp.g[which], y0, y1, y2);
         return;
     }
     if constexpr (NF == 3) {
@@ -426,7 +431,7 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     const double dz = a.dz_arg > 0.0 ? a.dz_arg : d.length_mm / a.nz;
     const double zb = a.dz_arg > 0.0 ? a.zbase : 0.0;
     if (flags & (A_RK_PREV | A_RK_THIS))
-        coupling_tile<R>(d, zb + (a.step - 1) * dz + 0.5 * dz, zb + a.step * dz, dz, cpl);
+        coupling_tile<R>(d, zb + a.zf_prev * dz, a.hf_prev * dz, zb + a.zf_this * dz, a.hf_this * dz, cpl);
 
     V v[NF][PF];
     // four-step twiddle W_nt^{j1 k2} of sample m; formed where it is used (before
@@ -592,7 +597,7 @@ __device__ __forceinline__ void row_tile(const StepArgs<R> &a, const InstDesc &d
     if (!(flags & B_FWD_ONLY)) {
         if (flags & B_DISP) {
             // H_f(k)/nt from the instance's table, laid out like the rows
-            const Phasor<R> *h = a.disp + d.disp_off + static_cast<long long>(f) * nt +
+            const Phasor<R> *h = a.disp + d.disp_off + static_cast<long long>(a.disp_sel * d.nf + f) * nt +
                                  static_cast<long long>(N) * k2 + t;
 #pragma unroll
             for (int m = 0; m < PF; ++m)
@@ -689,9 +694,10 @@ __global__ __launch_bounds__(kThreads, (mixed_min_blocks<R, CR, RR>())) void mix
 // row-pass order: position k2*n1 + k1 holds bin k = k2 + n2*k1.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void disp_table(const InstDesc *inst, int owner, Phasor<R> *out,
-                                                       double dz)
+                                                       double dz, int sel)
 {
     const InstDesc &d = inst[owner];
+    out += static_cast<long long>(sel) * d.nf * d.nt;     // table of the sel-th step size
     const long long n = static_cast<long long>(d.nf) * d.nt;
     for (long long q = blockIdx.x * static_cast<long long>(kThreads) + threadIdx.x; q < n;
          q += static_cast<long long>(gridDim.x) * kThreads) {

@@ -54,7 +54,7 @@ class OptionsT(ctypes.Structure):
                 ("state_bytes", ctypes.c_uint64), ("tile_a", ctypes.c_int32),
                 ("tile_b", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("record_rt", ctypes.c_int32),
-                ("n_crystals", ctypes.c_int32)]
+                ("n_crystals", ctypes.c_int32), ("split_order", ctypes.c_int32)]
 
 
 class OpoError(RuntimeError):
@@ -195,7 +195,7 @@ class Opo:
     """
 
     def __init__(self, instances, nz, precision="f32", device=0, tile_a=0, tile_b=0,
-                 use_graph=True, profile=False, record_rt=0):
+                 use_graph=True, profile=False, record_rt=0, split_order=2):
         import torch
         lib = load()
         self._lib = lib
@@ -214,7 +214,7 @@ class Opo:
                        state=ctypes.c_void_p(self._state.data_ptr()), state_bytes=nbytes,
                        tile_a=int(tile_a), tile_b=int(tile_b), use_graph=1 if use_graph else -1,
                        profile=1 if profile else 0, record_rt=int(record_rt),
-                       n_crystals=len(nz) if np.ndim(nz) else 1)
+                       n_crystals=len(nz) if np.ndim(nz) else 1, split_order=int(split_order))
         h = ctypes.c_void_p()
         _check(lib.opo_init_batch(ctypes.byref(h), self.n, fields, crystals, cavities,
                                   ctypes.byref(opt)))
