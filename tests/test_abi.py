@@ -126,3 +126,10 @@ def test_no_device_is_reported():
     rc, h = _init(f, c, k)
     assert rc == B.OPO_EDEVICE
     assert h.value is None
+
+
+def test_empty_batch_is_rejected():
+    n, f, c, k, keep = _one()
+    rc, h = _init(f, c, k, n=0)
+    assert rc == B.OPO_EINVAL and h.value is None
+    assert B.load().opo_state_bytes(0, f, 0) == 0

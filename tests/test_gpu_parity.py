@@ -287,3 +287,42 @@ def test_mixed_schedule_with_gdd_and_eom():
         for x in range(3):
             assert rel_l2(batch[i][0][x], ref[x]) <= 10 * TOL["f32"], (i, x)
             assert np.max(np.abs(batch[i][1][:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E["f32"]
+
+
+def test_fp64_mixed_schedule_batch():
+    """The FP64 kernels on the mixed schedule: a batch equals its single runs bit for bit and
+    the oracle to the FP64 bar."""
+    say("FP64 mixed batch")
+    insts = []
+    for b, nt in enumerate([2048, 4096, 2048, 4096]):
+        ins = _stress(nt, seed=90 + b)
+        ins["cavity"] = W.cavity(resonant=(0, 1, 0), refl=(0.0, 0.8 + 0.03 * b, 0.0), delta=(0.0, 0.2 * b, 0.0))
+        insts.append(ins)
+    nz, nrt = 6, 3
+    with B.Opo(insts, nz, precision="f64") as hb:
+        hb.cavity_roundtrip(nrt)
+        batch = [(hb.get_fields(i), hb.energy_history(i)) for i in range(len(insts))]
+    for i, ins in enumerate(insts):
+        with _handle(ins, nz, "f64") as h:
+            h.cavity_roundtrip(nrt)
+            assert np.array_equal(batch[i][0], h.get_fields())
+            assert np.array_equal(batch[i][1], h.energy_history())
+        ref, e_ref = oracle.roundtrips(ins["crystal"], ins["cavity"], ins["fields"], ins["pump_in"], nz, nrt)
+        for x in range(3):
+            assert rel_l2(batch[i][0][x], ref[x]) <= 10 * TOL["f64"], (i, x)
+            assert np.max(np.abs(batch[i][1][:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E["f64"]
+
+
+def test_zero_round_trips_and_bad_steps():
+    w = W.config("sro_cw", nt=256, nz=5)
+    with B.from_workload(w) as h:
+        a0 = h.get_fields()
+        h.cavity_roundtrip(0)
+        assert h.energy_history().shape == (0, 3)
+        assert np.array_equal(h.get_fields(), a0)
+        for nz, dz in ((0, 0.1), (3, 0.0), (3, -1.0), (3, float("nan"))):
+            with pytest.raises(B.OpoError) as ei:
+                h.ssfm_propagate(nz, dz)
+            assert ei.value.code == B.OPO_EINVAL
+        with pytest.raises(B.OpoError):
+            h.cavity_roundtrip(-1)
