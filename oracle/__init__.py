@@ -6,5 +6,5 @@ the benchmark use it. The GPU library never imports, links or calls it.
 from .oracle import (  # noqa: F401
     Crystal, Cavity, build, fft, ifft, kappa, kerr, omega, dispersion, rk4, linear,
     ssfm_pass, ssfm_pass_unsym, gdd, eom, roundtrips, roundtrips_record,
-    roundtrips_multi,
+    roundtrips_multi, propagate_adaptive,
 )

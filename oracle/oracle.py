@@ -115,6 +115,9 @@ def _load():
                                        ctypes.c_int, ctypes.c_int, P]
         lib.ora_roundtrips_rec.argtypes = [ctypes.POINTER(Crystal), ctypes.POINTER(Cavity), P, P,
                                            ctypes.c_int, ctypes.c_int, ctypes.c_int, P, P]
+        lib.ora_propagate_adaptive.argtypes = [ctypes.POINTER(Crystal), P, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_double, ctypes.c_int, P, P]
+        lib.ora_propagate_adaptive.restype = ctypes.c_int
         lib.ora_roundtrips_multi.argtypes = [ctypes.POINTER(Crystal), ctypes.c_int, P,
                                              ctypes.POINTER(Cavity), P, P, ctypes.c_int,
                                              ctypes.c_int, P, P]
@@ -274,3 +277,19 @@ def roundtrips_multi(crystals, nzs, cavity, a, pump_in, n_rt, record=False):
                                  _ptr(a), _ptr(p), p.size // nt, int(n_rt), _ptr(e),
                                  _ptr(rec) if record else None)
     return a, e, rec
+
+
+def propagate_adaptive(crystal, a, length, tol, dz0, max_steps=100000, z0=0.0):
+    """Propagation from z0 over `length` mm with the local-error adaptive step (second-order
+    steps only). Returns (fields, accepted steps, rejected steps); raises RuntimeError when
+    max_steps attempts do not reach the end."""
+    a = _fields(a, crystal)
+    acc, rej = ctypes.c_int(), ctypes.c_int()
+    rc = _load().ora_propagate_adaptive(ctypes.byref(Crystal.from_dict(crystal)), _ptr(a), float(z0),
+                                        float(length), float(tol), float(dz0), int(max_steps),
+                                        ctypes.byref(acc), ctypes.byref(rej))
+    if rc == -2:
+        raise ValueError("the adaptive step needs second-order steps (order 2)")
+    if rc != 0:
+        raise RuntimeError("adaptive propagation did not reach the end in %d attempts" % max_steps)
+    return a, acc.value, rej.value

@@ -1,0 +1,122 @@
+"""Pins of the oracle's adaptive step (local-error method, Sinkin et al. 2003; the paper
+keeps a fixed dz and points to that literature): each attempt compares one symmetrized
+step of dz with two of dz/2, d = ||u_f - u_c|| / ||u_f|| over all fields; d > 2 tol
+rejects and halves dz; otherwise (4 u_f - u_c)/3 is kept, and dz shrinks by 2^(1/3) when
+d > tol, grows by 2^(1/3) when d < tol/2. Every expectation below is built from the
+pinned fixed-step pass, never from the adaptive routine itself."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_02532_amd import workloads as W
+
+G = 2.0 ** (1.0 / 3.0)
+
+
+def _case(nt=128, deff=40.0, **kw):
+    """Pulsed pump with seeded signal and idler; mismatch, GVM, GVD and TOD on."""
+    cr = W.crystal(nt, t_window_ps=20.0, deff=deff, dk_per_mm=0.8, db1=(0.3, 0.0, -0.2),
+                   b2=(800.0, 500.0, 300.0), b3=(2000.0, 1000.0, 500.0), length_mm=2.0, **kw)
+    t = W.time_grid(nt, 20.0)
+    a = np.stack([2e6 * np.exp(-t * t / 8.0) + 0j,
+                  2e5 * np.exp(-(t - 1.0) ** 2 / 2.0) + W.noise(nt, 1e3, 3),
+                  W.noise(nt, 1e4, 4)])
+    return cr, a
+
+
+def _attempt(cr, u, z, h):
+    """One attempt from the fixed-step pass: (extrapolated result, d)."""
+    uc = oracle.ssfm_pass(cr, u, 1, h, z)
+    uf = oracle.ssfm_pass(cr, u, 2, 0.5 * h, z)
+    d = np.sqrt(np.sum(np.abs(uf - uc) ** 2) / np.sum(np.abs(uf) ** 2))
+    return (4.0 * uf - uc) / 3.0, d
+
+
+def test_linear_steps_grow_geometrically_and_end_exactly():
+    """Without coupling one step of dz and two of dz/2 are the same propagator, so d is
+    rounding, every attempt is kept and dz grows by 2^(1/3) each step; the last is cut
+    to end at L, and the result is the exact linear pass over L."""
+    cr, a = _case(deff=0.0)
+    L, dz0 = 2.0, 0.05
+    z, k = 0.0, 0
+    while z < L:                       # step count of the geometric sequence
+        z += dz0 * G ** k
+        k += 1
+    out, acc, rej = oracle.propagate_adaptive(cr, a, L, 1e-8, dz0)
+    assert (acc, rej) == (k, 0) and k == 11
+    ref = oracle.ssfm_pass(cr, a, 1, L)            # exact for the linear operator
+    assert np.max(np.abs(out - ref)) < 1e-12 * np.max(np.abs(a))
+
+
+def test_one_step_is_the_richardson_extrapolation():
+    """With dz0 >= L and a tolerance that keeps everything: one step cut to L, and the
+    result is (4 u_f - u_c)/3 of that step."""
+    cr, a = _case()
+    out, acc, rej = oracle.propagate_adaptive(cr, a, 2.0, 1e300, 5.0)
+    ref, _ = _attempt(cr, a, 0.0, 2.0)
+    assert (acc, rej) == (1, 0)
+    assert np.max(np.abs(out - ref)) <= 1e-14 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("ratio,branch", [(1.5, "shrink"), (0.75, "keep"), (1.0 / 3.0, "grow")])
+def test_accept_branches(ratio, branch):
+    """tol placed so that the first attempt's d = ratio tol falls in (tol, 2 tol],
+    [tol/2, tol] or below tol/2: it is kept and the second step is dz0 / 2^(1/3), dz0
+    or dz0 2^(1/3); a third, cut to dz0/2, ends the run."""
+    cr, a = _case()
+    dz0, z0 = 0.1, 0.3
+    u1, d1 = _attempt(cr, a, z0, dz0)
+    tol = d1 / ratio
+    h2 = {"shrink": dz0 / G, "keep": dz0, "grow": dz0 * G}[branch]
+    u2, d2 = _attempt(cr, u1, z0 + dz0, h2)
+    ref, d3 = _attempt(cr, u2, z0 + dz0 + h2, 0.5 * dz0)
+    assert d2 <= 2 * tol and d3 <= 2 * tol         # the later attempts are kept as well
+    out, acc, rej = oracle.propagate_adaptive(cr, a, dz0 + h2 + 0.5 * dz0, tol, dz0, z0=z0)
+    assert (acc, rej) == (3, 0)
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_reject_halves_the_step():
+    """d > 2 tol: the attempt is dropped and repeated with dz/2 from the same fields."""
+    cr, a = _case()
+    dz0 = 0.4
+    _, d1 = _attempt(cr, a, 0.0, dz0)
+    tol = 0.4 * d1
+    u1, dh = _attempt(cr, a, 0.0, 0.5 * dz0)
+    assert dh < 0.5 * tol                           # kept, then grown
+    ref, d2 = _attempt(cr, u1, 0.5 * dz0, 0.5 * dz0 * G)
+    assert d2 <= 2 * tol
+    out, acc, rej = oracle.propagate_adaptive(cr, a, 0.5 * dz0 * (1 + G), tol, dz0)
+    assert (acc, rej) == (2, 1)
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_attempt_budget():
+    """A tolerance no step meets rejects every attempt until the budget is spent."""
+    cr, a = _case()
+    with pytest.raises(RuntimeError):
+        oracle.propagate_adaptive(cr, a, 2.0, 1e-300, 0.1, max_steps=6)
+
+
+def test_error_follows_the_tolerance():
+    """On the nonlinear case the error against a converged fixed-step pass stays below
+    tol and falls as tol falls, while the step count rises about as tol^(-1/3)."""
+    cr, a = _case(nt=256)
+    L = 2.0
+    ref = oracle.ssfm_pass(cr, a, 4096, L / 4096)
+    rows = []
+    for tol in (1e-5, 1e-6, 1e-7):
+        out, acc, rej = oracle.propagate_adaptive(cr, a, L, tol, 0.05)
+        rows.append((tol, acc, np.linalg.norm(out - ref) / np.linalg.norm(ref)))
+    for tol, acc, err in rows:
+        assert err < tol, rows
+    assert rows[0][2] > rows[1][2] > rows[2][2], rows
+    assert 1.4 < rows[2][1] / rows[1][1] < 3.0, rows
+
+
+def test_zero_length_and_order_check():
+    cr, a = _case()
+    out, acc, rej = oracle.propagate_adaptive(cr, a, 0.0, 1e-6, 0.1)
+    assert (acc, rej) == (0, 0) and np.array_equal(out, a)
+    with pytest.raises(ValueError):
+        oracle.propagate_adaptive(dict(cr, order=4), a, 1.0, 1e-6, 0.1)
