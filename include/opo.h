@@ -51,7 +51,8 @@ typedef enum {
     OPO_ENOMEM = -2,     /* device or host allocation failed                    */
     OPO_EDEVICE = -3,    /* no usable gfx950 device, or a HIP call failed       */
     OPO_ENONFINITE = -4, /* a round-trip energy became NaN or Inf               */
-    OPO_ESTATE = -5      /* NULL or already destroyed handle, bad call order    */
+    OPO_ESTATE = -5,     /* NULL or already destroyed handle, bad call order    */
+    OPO_ESTEPS = -6      /* adaptive step: attempt budget spent before the end  */
 } opo_status;
 
 enum { OPO_F32 = 0, OPO_F64 = 1 };
@@ -181,6 +182,26 @@ int opo_init_batch(opo_t **h, int32_t n, const opo_fields_t *fields,
  * of nz/2 equal one of nz). No cavity operation. Asynchronous on the handle's
  * stream; opo_sync waits. */
 int ssfm_propagate(opo_t *h, int32_t nz, double dz);
+
+/* Propagation of every instance over length_mm [mm] from the handle's z with
+ * the step chosen per instance by the local-error method (the adaptive step
+ * the paper leaves to the user, Sec. 1, for its fixed-step Sec. 2.2): an
+ * attempt from z compares one symmetrized step of dz with two of dz/2;
+ * d = ||u_f - u_c|| / ||u_f|| over all fields of the instance. d > 2 tol
+ * rejects the attempt and halves dz; otherwise the fields become
+ * (4 u_f - u_c)/3, z advances by dz, and dz is divided by 2^(1/3) if d > tol,
+ * multiplied by it if d < tol/2. The first attempt uses dz0; a step that would
+ * pass the end (or stop within 1e-9 dz of it) ends there. max_attempts counts
+ * accepted and rejected attempts per instance. Needs split_order 2; uses
+ * crystal 0; no cavity operation. accepted, rejected and z_end (n entries
+ * each, or NULL) receive each instance's counts and the z it reached. Returns
+ * OPO_ESTEPS if an instance spent its budget first (its fields then hold the
+ * last accepted step, at z_end); the handle's z advances by length_mm. The
+ * first call allocates two state-sized copies and per-instance propagator
+ * tables (4x the state in FP32, 2x in FP64) kept until opo_destroy.
+ * Synchronizes the stream. */
+int ssfm_propagate_adaptive(opo_t *h, double length_mm, double tol, double dz0, int32_t max_attempts,
+                            int32_t *accepted, int32_t *rejected, double *z_end);
 
 /* n_rt cavity round trips (Sec. 4.1): read the input pump into a non-resonant
  * pump and zero non-resonant signal/idler, one pass of crystal.nz steps with

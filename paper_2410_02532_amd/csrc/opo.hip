@@ -183,6 +183,12 @@ struct opo_s {
     int use_graph = 1;
     hipGraphExec_t graph = nullptr;
     void *scratch = nullptr;         // spectrum read-out
+    // adaptive step: coarse and fine copies of the state, per-instance
+    // propagator tables (coarse and fine step), control state, error partials
+    void *a_uc = nullptr, *a_uf = nullptr, *a_tab = nullptr;
+    AdaptState *d_actl = nullptr;
+    double *d_apart = nullptr;
+    int a_chunks = 0;
     std::vector<double> t_window;    // T of every instance [ps]
     // profile option: event pairs of the launches since the last collection
     bool profile = false;
@@ -389,7 +395,8 @@ static void release(opo_t *h)
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->own_state && h->state) (void)hipFree(h->state);
     void *bufs[] = {h->pump, h->d_inst, h->d_tile_a, h->d_tile_b, h->d_tw, h->d_tw4, h->d_disp, h->d_map[0], h->d_map[1],
-                    h->d_partial, h->d_hist, h->d_counter, h->scratch, h->d_record};
+                    h->d_partial, h->d_hist, h->d_counter, h->scratch, h->d_record,
+                    h->a_uc, h->a_uf, h->a_tab, h->d_actl, h->d_apart};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (hipEvent_t e : h->events)
@@ -508,12 +515,13 @@ template <typename R> static void launch_a(opo_t *h, StepArgs<R> a, int flags, i
     prof_end(h);
 }
 
-template <typename R> static void launch_b(opo_t *h, StepArgs<R> a, int flags, int step = 0)
+template <typename R> static void launch_b(opo_t *h, StepArgs<R> a, int flags, int step = 0, int sel = -1)
 {
     a.tile_inst = h->d_tile_b;
     a.flags = flags;
     double z, tau;
     substep(h, step, z, tau, a.disp_sel);
+    if (sel >= 0) a.disp_sel = sel;
     prof_begin(h, OPO_K_ROW);
     for (const Group &g : h->groups_b) {
         a.tile0 = g.tile0;
@@ -1028,6 +1036,89 @@ template <typename R> static int propagate_impl(opo_t *h, int nz, double dz)
     return prof_collect(h, used);
 }
 
+// Adaptive step: every instance from the handle's z over `length` (see
+// adapt_control for the step control). Attempts are queued in chunks; the
+// control state is read back after each chunk to see whether all have
+// stopped.
+template <typename R>
+static int adaptive_impl(opo_t *h, double length, double tol, double dz0, int max_attempts, int32_t *accepted,
+                         int32_t *rejected, double *z_end)
+{
+    const size_t n_elem = h->state_bytes / h->elem;
+    if (!h->a_uc) {
+        long long max_n = 0;
+        for (const InstDesc &d : h->inst)
+            max_n = std::max(max_n, static_cast<long long>(d.nf) * d.nt);
+        h->a_chunks = static_cast<int>(std::min<long long>((max_n + 8LL * kThreads - 1) / (8LL * kThreads), 256));
+        if (static_cast<long long>(h->a_chunks) * h->n_inst > 2147483647LL)
+            return fail(OPO_EINVAL, "too many instances for the adaptive step");
+        if (hipMalloc(&h->a_uc, h->state_bytes) != hipSuccess || hipMalloc(&h->a_uf, h->state_bytes) != hipSuccess ||
+            hipMalloc(&h->a_tab, 2 * n_elem * sizeof(Phasor<R>)) != hipSuccess ||
+            hipMalloc(&h->d_actl, h->n_inst * sizeof(AdaptState)) != hipSuccess ||
+            hipMalloc(&h->d_apart, 2 * sizeof(double) * h->a_chunks * h->n_inst) != hipSuccess)
+            return fail(OPO_ENOMEM, "hipMalloc of the adaptive-step buffers failed");
+    }
+    const int blocks = h->a_chunks * h->n_inst;
+    cplx<R> *u = static_cast<cplx<R> *>(h->state), *uc = static_cast<cplx<R> *>(h->a_uc),
+            *uf = static_cast<cplx<R> *>(h->a_uf);
+    Phasor<R> *tab = static_cast<Phasor<R> *>(h->a_tab);
+    adapt_control<<<1, kThreads, 0, h->stream>>>(h->d_actl, h->n_inst, h->a_chunks, h->d_apart, 0, h->z, length,
+                                                 dz0, tol, max_attempts);
+    StepArgs<R> a = base_args<R>(h, h->a_uc);
+    a.adapt = h->d_actl;
+    a.disp = tab;
+    std::vector<AdaptState> ctl(h->n_inst);
+    int chunk = 4;
+    for (long long done = 0;;) {
+        for (int r = 0; r < chunk; ++r) {
+            adapt_begin<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, h->d_actl, h->a_chunks, u, uc, uf, tab);
+            a.state = uc;                 // one step of dz
+            a.adapt_scale = 1.0;
+            launch_a<R>(h, a, A_RK_THIS | A_FWD, 0);
+            launch_b<R>(h, a, B_DISP, 0, 0);
+            launch_a<R>(h, a, A_INV | A_RK_PREV, 1);
+            a.state = uf;                 // two steps of dz/2
+            a.adapt_scale = 0.5;
+            launch_a<R>(h, a, A_RK_THIS | A_FWD, 0);
+            launch_b<R>(h, a, B_DISP, 0, 1);
+            launch_a<R>(h, a, A_INV | A_RK_PREV | A_RK_THIS | A_FWD, 1);
+            launch_b<R>(h, a, B_DISP, 1, 1);
+            launch_a<R>(h, a, A_INV | A_RK_PREV, 2);
+            adapt_error<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, h->d_actl, h->a_chunks, uc, uf, h->d_apart);
+            adapt_control<<<1, kThreads, 0, h->stream>>>(h->d_actl, h->n_inst, h->a_chunks, h->d_apart, 1, 0.0, 0.0,
+                                                         0.0, tol, max_attempts);
+        }
+        HIP_TRY(hipGetLastError());
+        done += chunk;
+        HIP_TRY(hipMemcpyAsync(ctl.data(), h->d_actl, ctl.size() * sizeof(AdaptState), hipMemcpyDeviceToHost,
+                               h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        const size_t used = h->ev_used;
+        h->ev_used = 0;
+        int prc = prof_collect(h, used);
+        if (prc) return prc;
+        bool running = false;
+        for (const AdaptState &st : ctl)
+            running = running || st.status == 0;
+        if (!running) break;
+        chunk = static_cast<int>(std::min<long long>(std::max<long long>(done, 4), 64));
+    }
+    // extrapolate the steps kept by the last attempts
+    adapt_begin<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, h->d_actl, h->a_chunks, u, uc, uf, tab);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    bool spent = false;
+    for (int i = 0; i < h->n_inst; ++i) {
+        if (accepted) accepted[i] = ctl[i].accepted;
+        if (rejected) rejected[i] = ctl[i].rejected;
+        if (z_end) z_end[i] = ctl[i].z;
+        spent = spent || ctl[i].status == 2;
+    }
+    h->z += length;
+    if (spent) return fail(OPO_ESTEPS, "adaptive step: attempt budget spent before the end");
+    return OPO_OK;
+}
+
 template <typename R> static int roundtrip_impl(opo_t *h, int n_rt)
 {
     int trc = ensure_tables<R>(h, 0.0);
@@ -1151,6 +1242,24 @@ int ssfm_propagate(opo_t *h, int32_t nz, double dz)
         return h->precision == OPO_F64 ? propagate_impl<double>(h, nz, dz) : propagate_impl<float>(h, nz, dz);
     } catch (...) {
         return fail(OPO_EDEVICE, "unexpected exception in ssfm_propagate");
+    }
+}
+
+int ssfm_propagate_adaptive(opo_t *h, double length_mm, double tol, double dz0, int32_t max_attempts,
+                            int32_t *accepted, int32_t *rejected, double *z_end)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    if (!(length_mm >= 0.0) || !std::isfinite(length_mm) || !(tol > 0.0) || !std::isfinite(tol) ||
+        !(dz0 > 0.0) || !std::isfinite(dz0) || max_attempts < 1)
+        return fail(OPO_EINVAL, "need finite length_mm >= 0, tol > 0, dz0 > 0 and max_attempts >= 1");
+    if (h->order != 2) return fail(OPO_EINVAL, "the adaptive step needs split_order 2");
+    try {
+        return h->precision == OPO_F64
+                   ? adaptive_impl<double>(h, length_mm, tol, dz0, max_attempts, accepted, rejected, z_end)
+                   : adaptive_impl<float>(h, length_mm, tol, dz0, max_attempts, accepted, rejected, z_end);
+    } catch (...) {
+        return fail(OPO_EDEVICE, "unexpected exception in ssfm_propagate_adaptive");
     }
 }
 

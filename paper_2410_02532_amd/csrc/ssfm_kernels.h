@@ -84,6 +84,19 @@ enum : int {
     B_FWD_ONLY = 4,   // forward row FFT only (spectrum read-out)
 };
 
+// Step control of one instance under the adaptive step (local-error method,
+// the step-size scheme of the literature the paper points to), FP64.
+struct AdaptState {
+    double z;            // position reached by the accepted steps
+    double end;          // where the propagation ends
+    double dz;           // step of the next attempt (already cut at the end)
+    int status;          // 0 running, 1 reached the end, 2 attempt budget spent
+    int last;            // the next attempt ends at `end`
+    int pend;            // the last attempt was kept: the coarse and fine
+                         // buffers hold a step still to be extrapolated
+    int accepted, rejected;
+};
+
 template <typename R> struct StepArgs {
     const InstDesc *inst;
     const int *tile_inst;     // tile -> instance
@@ -109,6 +122,11 @@ template <typename R> struct StepArgs {
     // second half of the previous step starts at zf_prev with size hf_prev,
     // the first half of this step at zf_this with size hf_this (z from zbase)
     double zf_prev, hf_prev, zf_this, hf_this;
+    // adaptive step: per-instance z and dz (instances not running skip their
+    // tiles), the launch's step is adapt_scale * dz, and the propagator tables
+    // are per instance at 2 * off (coarse dz, then fine dz/2)
+    const AdaptState *adapt;
+    double adapt_scale;
 };
 
 // ---------------------------------------------------------------- shapes --
@@ -428,8 +446,13 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     const bool act = j1 < n1;
     V *g = a.state + d.off + j1;
 
-    const double dz = a.dz_arg > 0.0 ? a.dz_arg : d.length_mm / a.nz;
-    const double zb = a.dz_arg > 0.0 ? a.zbase : 0.0;
+    double dz = a.dz_arg > 0.0 ? a.dz_arg : d.length_mm / a.nz;
+    double zb = a.dz_arg > 0.0 ? a.zbase : 0.0;
+    if (a.adapt) {
+        const AdaptState &st = a.adapt[a.tile_inst[tile]];
+        dz = st.dz * a.adapt_scale;
+        zb = st.z;
+    }
     if (flags & (A_RK_PREV | A_RK_THIS))
         coupling_tile<R>(d, zb + a.zf_prev * dz, a.hf_prev * dz, zb + a.zf_this * dz, a.hf_this * dz, cpl);
 
@@ -562,6 +585,7 @@ __global__ __launch_bounds__(kThreads) void column_pass(StepArgs<R> a)
     __shared__ Coupling<R> cpl;
     __shared__ double red[3 * kThreads / 64];
     const int tile = a.tile0 + blockIdx.x;
+    if (a.adapt && a.adapt[a.tile_inst[tile]].status != 0) return;
     column_dispatch<R, LO, HI, NF>(a, a.inst[a.tile_inst[tile]], tile, reinterpret_cast<cplx<R> *>(lds_raw),
                                    &cpl, red);
 }
@@ -597,7 +621,8 @@ __device__ __forceinline__ void row_tile(const StepArgs<R> &a, const InstDesc &d
     if (!(flags & B_FWD_ONLY)) {
         if (flags & B_DISP) {
             // H_f(k)/nt from the instance's table, laid out like the rows
-            const Phasor<R> *h = a.disp + d.disp_off + static_cast<long long>(a.disp_sel * d.nf + f) * nt +
+            const long long toff = a.adapt ? 2LL * d.off : d.disp_off;
+            const Phasor<R> *h = a.disp + toff + static_cast<long long>(a.disp_sel * d.nf + f) * nt +
                                  static_cast<long long>(N) * k2 + t;
 #pragma unroll
             for (int m = 0; m < PF; ++m)
@@ -639,6 +664,7 @@ __global__ __launch_bounds__(kThreads) void row_pass(StepArgs<R> a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int tile = a.tile0 + blockIdx.x;
+    if (a.adapt && a.adapt[a.tile_inst[tile]].status != 0) return;
     row_dispatch<R, LO, HI>(a, a.inst[a.tile_inst[tile]], tile, reinterpret_cast<cplx<R> *>(lds_raw));
 }
 
@@ -692,6 +718,19 @@ __global__ __launch_bounds__(kThreads, (mixed_min_blocks<R, CR, RR>())) void mix
 // H_x(k)/nt = exp{[-alpha_x/2 + i(-db1 w + b2 w^2/2 - b3 w^3/6)] dz}/nt,
 // formed in FP64 (phase reduced modulo one revolution) and stored in the
 // row-pass order: position k2*n1 + k1 holds bin k = k2 + n2*k1.
+template <typename R> __device__ __forceinline__ Phasor<R> propagator(const InstDesc &d, long long q, double dz)
+{
+    const int f = static_cast<int>(q / d.nt);
+    const int p = static_cast<int>(q - static_cast<long long>(f) * d.nt);
+    const int k2 = p >> d.log2n1, k1 = p & (d.n1 - 1);
+    const int k = k2 + d.n2 * k1;
+    const double ks = static_cast<double>(k < (d.nt >> 1) ? k : k - d.nt);
+    const double rho = dz * ks * (d.disp[f][0] + ks * (d.disp[f][1] + ks * d.disp[f][2]));
+    const double amp = exp(-d.alpha_half[f] * dz) / d.nt;
+    const double2 e = unit_rev(rho);
+    return make_phasor<R>(amp * e.x, amp * e.y);
+}
+
 template <typename R>
 __global__ __launch_bounds__(kThreads) void disp_table(const InstDesc *inst, int owner, Phasor<R> *out,
                                                        double dz, int sel)
@@ -700,16 +739,133 @@ __global__ __launch_bounds__(kThreads) void disp_table(const InstDesc *inst, int
     out += static_cast<long long>(sel) * d.nf * d.nt;     // table of the sel-th step size
     const long long n = static_cast<long long>(d.nf) * d.nt;
     for (long long q = blockIdx.x * static_cast<long long>(kThreads) + threadIdx.x; q < n;
-         q += static_cast<long long>(gridDim.x) * kThreads) {
-        const int f = static_cast<int>(q / d.nt);
-        const int p = static_cast<int>(q - static_cast<long long>(f) * d.nt);
-        const int k2 = p >> d.log2n1, k1 = p & (d.n1 - 1);
-        const int k = k2 + d.n2 * k1;
-        const double ks = static_cast<double>(k < (d.nt >> 1) ? k : k - d.nt);
-        const double rho = dz * ks * (d.disp[f][0] + ks * (d.disp[f][1] + ks * d.disp[f][2]));
-        const double amp = exp(-d.alpha_half[f] * dz) / d.nt;
-        const double2 e = unit_rev(rho);
-        out[d.disp_off + q] = make_phasor<R>(amp * e.x, amp * e.y);
+         q += static_cast<long long>(gridDim.x) * kThreads)
+        out[d.disp_off + q] = propagator<R>(d, q, dz);
+}
+
+// ------------------------------------------------------------------------
+// Adaptive step (local-error method). Every attempt of a running instance
+// takes one symmetrized step of dz on a copy u_c and two of dz/2 on a copy
+// u_f; d = ||u_f - u_c|| / ||u_f|| over all its fields decides: d > 2 tol
+// rejects and halves dz; otherwise (4 u_f - u_c)/3 becomes the fields, z
+// advances, and dz shrinks by 2^(1/3) when d > tol, grows by 2^(1/3) when
+// d < tol/2. The kernels below run once per attempt around the step
+// launches: begin, [coarse, fine passes], error, control. Each of begin and
+// error covers instance b / chunks with `chunks` workgroups.
+constexpr double kAdaptGrow = 1.25992104989487316477;   // 2^(1/3), the nearest double
+constexpr double kAdaptSlack = 1.0 + 1e-9;   // a step that stops within 1e-9 dz of the end goes to it
+
+// Fields of the attempt: the extrapolation of the step kept by the previous
+// attempt (also for instances that have just stopped), copied to u_c and u_f
+// for a running instance, with its coarse and fine propagator tables.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void adapt_begin(const InstDesc *inst, const AdaptState *ctl, int chunks,
+                                                        cplx<R> *u, cplx<R> *uc, cplx<R> *uf, Phasor<R> *tab)
+{
+    using V = cplx<R>;
+    const int ii = blockIdx.x / chunks, ch = blockIdx.x - ii * chunks;
+    const AdaptState st = ctl[ii];
+    const bool run = st.status == 0;
+    if (!run && !st.pend) return;
+    const InstDesc &d = inst[ii];
+    const long long n = static_cast<long long>(d.nf) * d.nt;
+    for (long long q = ch * static_cast<long long>(kThreads) + threadIdx.x; q < n;
+         q += static_cast<long long>(chunks) * kThreads) {
+        const long long j = d.off + q;
+        V x;
+        if (st.pend) {
+            const V f = uf[j], c = uc[j];
+            x = mk<V>((R(4) * f.x - c.x) / R(3), (R(4) * f.y - c.y) / R(3));
+            u[j] = x;
+        } else {
+            x = u[j];
+        }
+        if (run) {
+            uc[j] = x;
+            uf[j] = x;
+            tab[2 * d.off + q] = propagator<R>(d, q, st.dz);
+            tab[2 * d.off + n + q] = propagator<R>(d, q, 0.5 * st.dz);
+        }
+    }
+}
+
+// FP64 partial sums of |u_f - u_c|^2 and |u_f|^2 of each running instance.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void adapt_error(const InstDesc *inst, const AdaptState *ctl, int chunks,
+                                                        const cplx<R> *uc, const cplx<R> *uf, double *part)
+{
+    __shared__ double red[3 * kThreads / 64];
+    const int ii = blockIdx.x / chunks, ch = blockIdx.x - ii * chunks;
+    if (ctl[ii].status != 0) return;
+    const InstDesc &d = inst[ii];
+    const long long n = static_cast<long long>(d.nf) * d.nt;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (long long q = ch * static_cast<long long>(kThreads) + threadIdx.x; q < n;
+         q += static_cast<long long>(chunks) * kThreads) {
+        const double fx = uf[d.off + q].x, fy = uf[d.off + q].y;
+        const double ex = fx - static_cast<double>(uc[d.off + q].x), ey = fy - static_cast<double>(uc[d.off + q].y);
+        v[0] += ex * ex + ey * ey;
+        v[1] += fx * fx + fy * fy;
+    }
+    block_sum3(v, red);
+    if (threadIdx.x == 0) {
+        part[2 * static_cast<long long>(blockIdx.x)] = v[0];
+        part[2 * static_cast<long long>(blockIdx.x) + 1] = v[1];
+    }
+}
+
+// One thread per instance. mode 0 starts a run from z0 over `length` with
+// step dz0; mode 1 takes the decision of the attempt just made. Both then
+// prepare the next attempt: stop at the end or when the budget is spent,
+// else cut a step that would pass the end.
+__global__ __launch_bounds__(kThreads) void adapt_control(AdaptState *ctl, int n_inst, int chunks,
+                                                          const double *part, int mode, double z0, double length,
+                                                          double dz0, double tol, int max_attempts)
+{
+    for (int ii = threadIdx.x; ii < n_inst; ii += kThreads) {
+        AdaptState st = ctl[ii];
+        if (mode == 0) {
+            st.z = z0;
+            st.end = z0 + length;
+            st.dz = dz0;
+            st.status = 0;
+            st.last = 0;
+            st.pend = 0;
+            st.accepted = 0;
+            st.rejected = 0;
+        } else if (st.status == 0) {
+            double num = 0.0, den = 0.0;
+            for (int c = 0; c < chunks; ++c) {
+                num += part[2 * (static_cast<long long>(ii) * chunks + c)];
+                den += part[2 * (static_cast<long long>(ii) * chunks + c) + 1];
+            }
+            const double dd = sqrt(num / den);
+            if (dd > 2.0 * tol) {
+                st.dz *= 0.5;
+                st.rejected += 1;
+                st.pend = 0;
+            } else {
+                st.z = st.last ? st.end : st.z + st.dz;
+                st.accepted += 1;
+                st.pend = 1;
+                if (dd > tol) st.dz /= kAdaptGrow;
+                else if (dd < 0.5 * tol) st.dz *= kAdaptGrow;
+            }
+        } else {
+            st.pend = 0;      // extrapolated by the begin of this attempt
+        }
+        if (st.status == 0) {
+            if (!(st.z < st.end)) {
+                st.status = 1;
+            } else if (st.accepted + st.rejected >= max_attempts) {
+                st.status = 2;
+            } else {
+                const double rest = st.end - st.z;
+                st.last = rest <= st.dz * kAdaptSlack;
+                if (st.last) st.dz = rest;
+            }
+        }
+        ctl[ii] = st;
     }
 }
 

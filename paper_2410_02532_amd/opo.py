@@ -12,12 +12,13 @@ import numpy as np
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libopo.so")
 
-OPO_OK, OPO_EINVAL, OPO_ENOMEM, OPO_EDEVICE, OPO_ENONFINITE, OPO_ESTATE = 0, -1, -2, -3, -4, -5
+OPO_OK, OPO_EINVAL, OPO_ENOMEM, OPO_EDEVICE, OPO_ENONFINITE, OPO_ESTATE, OPO_ESTEPS = 0, -1, -2, -3, -4, -5, -6
 OPO_F32, OPO_F64 = 0, 1
 STATUS = {0: "OPO_OK", -1: "OPO_EINVAL", -2: "OPO_ENOMEM", -3: "OPO_EDEVICE",
-          -4: "OPO_ENONFINITE", -5: "OPO_ESTATE"}
+          -4: "OPO_ENONFINITE", -5: "OPO_ESTATE", -6: "OPO_ESTEPS"}
 
-EXPORTS = ("opo_state_bytes", "opo_init", "opo_init_batch", "ssfm_propagate", "cavity_roundtrip",
+EXPORTS = ("opo_state_bytes", "opo_init", "opo_init_batch", "ssfm_propagate", "ssfm_propagate_adaptive",
+           "cavity_roundtrip",
            "opo_sync", "opo_get_fields", "opo_set_fields", "opo_get_energy_history",
            "opo_get_record", "opo_get_grid", "opo_kernel_times", "opo_info", "opo_destroy",
            "opo_last_error")
@@ -83,6 +84,7 @@ def load():
                                    ctypes.POINTER(CrystalT), ctypes.POINTER(CavityT),
                                    ctypes.POINTER(OptionsT)]
     lib.ssfm_propagate.argtypes = [P, I, D]
+    lib.ssfm_propagate_adaptive.argtypes = [P, D, D, D, I, P, P, P]
     lib.cavity_roundtrip.argtypes = [P, I]
     lib.opo_sync.argtypes = [P]
     lib.opo_get_fields.argtypes = [P, I, I, I, P]
@@ -95,7 +97,8 @@ def load():
     lib.opo_destroy.argtypes = [P]
     lib.opo_last_error.argtypes = []
     lib.opo_last_error.restype = ctypes.c_char_p
-    for name in ("opo_init", "opo_init_batch", "ssfm_propagate", "cavity_roundtrip", "opo_sync",
+    for name in ("opo_init", "opo_init_batch", "ssfm_propagate", "ssfm_propagate_adaptive",
+                 "cavity_roundtrip", "opo_sync",
                  "opo_get_fields", "opo_set_fields", "opo_get_energy_history", "opo_get_record",
                  "opo_get_grid",
                  "opo_kernel_times", "opo_info", "opo_destroy"):
@@ -224,6 +227,19 @@ class Opo:
     # --- the three calls of the boundary
     def ssfm_propagate(self, nz, dz):
         _check(self._lib.ssfm_propagate(self.h, int(nz), float(dz)))
+
+    def ssfm_propagate_adaptive(self, length, tol, dz0, max_attempts=100000):
+        """Adaptive-step propagation of every instance over `length` mm (local-error
+        method). Returns (accepted, rejected, z_end) arrays, one entry per instance;
+        raises OpoError (OPO_ESTEPS) when an instance spends max_attempts first."""
+        n = len(self.nts)
+        acc = np.zeros(n, np.int32)
+        rej = np.zeros(n, np.int32)
+        zend = np.zeros(n, np.float64)
+        _check(self._lib.ssfm_propagate_adaptive(self.h, float(length), float(tol), float(dz0),
+                                                 int(max_attempts), acc.ctypes.data, rej.ctypes.data,
+                                                 zend.ctypes.data))
+        return acc, rej, zend
 
     def cavity_roundtrip(self, n_rt):
         return _check(self._lib.cavity_roundtrip(self.h, int(n_rt)))
