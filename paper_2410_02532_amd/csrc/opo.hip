@@ -189,6 +189,7 @@ struct opo_s {
     AdaptState *d_actl = nullptr;
     double *d_apart = nullptr;
     int a_chunks = 0;
+    hipGraphExec_t a_graph = nullptr;   // one attempt, replayed (reads everything from the device)
     std::vector<double> t_window;    // T of every instance [ps]
     // profile option: event pairs of the launches since the last collection
     bool profile = false;
@@ -393,6 +394,7 @@ static void release(opo_t *h)
     (void)hipSetDevice(h->device);
     if (h->stream) (void)hipStreamSynchronize(h->stream);
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
+    if (h->a_graph) (void)hipGraphExecDestroy(h->a_graph);
     if (h->own_state && h->state) (void)hipFree(h->state);
     void *bufs[] = {h->pump, h->d_inst, h->d_tile_a, h->d_tile_b, h->d_tw, h->d_tw4, h->d_disp, h->d_map[0], h->d_map[1],
                     h->d_partial, h->d_hist, h->d_counter, h->scratch, h->d_record,
@@ -1040,6 +1042,43 @@ template <typename R> static int propagate_impl(opo_t *h, int nz, double dz)
 // adapt_control for the step control). Attempts are queued in chunks; the
 // control state is read back after each chunk to see whether all have
 // stopped.
+// One attempt of the adaptive step for every running instance: begin, one
+// step of dz on the coarse copy, two of dz/2 on the fine copy, the error
+// sums and the control decision. Every launch argument is fixed once the
+// buffers exist (z, dz, tol and the budget live in the control state), so
+// the sequence is captured once into a graph and replayed.
+template <typename R> static void enqueue_attempt(opo_t *h)
+{
+    const int blocks = h->a_chunks * h->n_inst;
+    cplx<R> *u = static_cast<cplx<R> *>(h->state), *uc = static_cast<cplx<R> *>(h->a_uc),
+            *uf = static_cast<cplx<R> *>(h->a_uf);
+    Phasor<R> *tab = static_cast<Phasor<R> *>(h->a_tab);
+    StepArgs<R> a = base_args<R>(h, h->a_uc);
+    a.adapt = h->d_actl;
+    a.disp = tab;
+    adapt_begin<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, h->d_actl, h->a_chunks, u, uc, uf, tab);
+    a.state = uc;                 // one step of dz
+    a.adapt_scale = 1.0;
+    launch_a<R>(h, a, A_RK_THIS | A_FWD, 0);
+    launch_b<R>(h, a, B_DISP, 0, 0);
+    launch_a<R>(h, a, A_INV | A_RK_PREV, 1);
+    a.state = uf;                 // two steps of dz/2
+    a.adapt_scale = 0.5;
+    launch_a<R>(h, a, A_RK_THIS | A_FWD, 0);
+    launch_b<R>(h, a, B_DISP, 0, 1);
+    launch_a<R>(h, a, A_INV | A_RK_PREV | A_RK_THIS | A_FWD, 1);
+    launch_b<R>(h, a, B_DISP, 1, 1);
+    launch_a<R>(h, a, A_INV | A_RK_PREV, 2);
+    adapt_error<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, h->d_actl, h->a_chunks, uc, uf, h->d_apart);
+    adapt_control<<<(h->n_inst + kThreads / 64 - 1) / (kThreads / 64), kThreads, 0, h->stream>>>(h->d_actl, h->n_inst, h->a_chunks, h->d_apart, 1, 0.0, 0.0, 0.0,
+                                                 0.0, 0);
+}
+
+// Adaptive step: every instance from the handle's z over `length` (see
+// adapt_control for the step control). Attempts are queued in chunks sized
+// by the remaining distance over the current step of the slowest instance;
+// the control state is read back after each chunk to see whether all have
+// stopped.
 template <typename R>
 static int adaptive_impl(opo_t *h, double length, double tol, double dz0, int max_attempts, int32_t *accepted,
                          int32_t *rejected, double *z_end)
@@ -1059,37 +1098,47 @@ static int adaptive_impl(opo_t *h, double length, double tol, double dz0, int ma
             return fail(OPO_ENOMEM, "hipMalloc of the adaptive-step buffers failed");
     }
     const int blocks = h->a_chunks * h->n_inst;
-    cplx<R> *u = static_cast<cplx<R> *>(h->state), *uc = static_cast<cplx<R> *>(h->a_uc),
-            *uf = static_cast<cplx<R> *>(h->a_uf);
-    Phasor<R> *tab = static_cast<Phasor<R> *>(h->a_tab);
-    adapt_control<<<1, kThreads, 0, h->stream>>>(h->d_actl, h->n_inst, h->a_chunks, h->d_apart, 0, h->z, length,
+    if (h->use_graph && !h->a_graph) {
+        hipGraph_t g;
+        HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        enqueue_attempt<R>(h);
+        hipError_t ce = hipStreamEndCapture(h->stream, &g);
+        if (ce != hipSuccess) return fail(OPO_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+        ce = hipGraphInstantiate(&h->a_graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ce != hipSuccess) {
+            h->a_graph = nullptr;
+            return fail(OPO_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ce));
+        }
+    }
+    adapt_control<<<(h->n_inst + kThreads / 64 - 1) / (kThreads / 64), kThreads, 0, h->stream>>>(h->d_actl, h->n_inst, h->a_chunks, h->d_apart, 0, h->z, length,
                                                  dz0, tol, max_attempts);
-    StepArgs<R> a = base_args<R>(h, h->a_uc);
-    a.adapt = h->d_actl;
-    a.disp = tab;
     std::vector<AdaptState> ctl(h->n_inst);
-    int chunk = 4;
-    for (long long done = 0;;) {
+    HIP_TRY(hipMemcpyAsync(ctl.data(), h->d_actl, ctl.size() * sizeof(AdaptState), hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (;;) {
+        // attempts the slowest running instance needs at least: its steps
+        // growing by 2^(1/3) each time reach the end after n with
+        // dz (g^n - 1)/(g - 1) >= rest (at least one, at most 64 per chunk)
+        double need = 0.0;
+        bool running = false;
+        for (const AdaptState &st : ctl)
+            if (st.status == 0) {
+                running = true;
+                const double n = std::log1p((st.end - st.z) * (kAdaptGrow - 1.0) / st.dz) / std::log(kAdaptGrow);
+                need = std::max(need, std::ceil(n - 1e-9));
+            }
+        if (!running) break;
+        const int chunk = static_cast<int>(std::min(std::max(need, 1.0), 64.0));
         for (int r = 0; r < chunk; ++r) {
-            adapt_begin<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, h->d_actl, h->a_chunks, u, uc, uf, tab);
-            a.state = uc;                 // one step of dz
-            a.adapt_scale = 1.0;
-            launch_a<R>(h, a, A_RK_THIS | A_FWD, 0);
-            launch_b<R>(h, a, B_DISP, 0, 0);
-            launch_a<R>(h, a, A_INV | A_RK_PREV, 1);
-            a.state = uf;                 // two steps of dz/2
-            a.adapt_scale = 0.5;
-            launch_a<R>(h, a, A_RK_THIS | A_FWD, 0);
-            launch_b<R>(h, a, B_DISP, 0, 1);
-            launch_a<R>(h, a, A_INV | A_RK_PREV | A_RK_THIS | A_FWD, 1);
-            launch_b<R>(h, a, B_DISP, 1, 1);
-            launch_a<R>(h, a, A_INV | A_RK_PREV, 2);
-            adapt_error<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, h->d_actl, h->a_chunks, uc, uf, h->d_apart);
-            adapt_control<<<1, kThreads, 0, h->stream>>>(h->d_actl, h->n_inst, h->a_chunks, h->d_apart, 1, 0.0, 0.0,
-                                                         0.0, tol, max_attempts);
+            if (h->a_graph) {
+                HIP_TRY(hipGraphLaunch(h->a_graph, h->stream));
+            } else {
+                enqueue_attempt<R>(h);
+            }
         }
         HIP_TRY(hipGetLastError());
-        done += chunk;
         HIP_TRY(hipMemcpyAsync(ctl.data(), h->d_actl, ctl.size() * sizeof(AdaptState), hipMemcpyDeviceToHost,
                                h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
@@ -1097,14 +1146,12 @@ static int adaptive_impl(opo_t *h, double length, double tol, double dz0, int ma
         h->ev_used = 0;
         int prc = prof_collect(h, used);
         if (prc) return prc;
-        bool running = false;
-        for (const AdaptState &st : ctl)
-            running = running || st.status == 0;
-        if (!running) break;
-        chunk = static_cast<int>(std::min<long long>(std::max<long long>(done, 4), 64));
     }
     // extrapolate the steps kept by the last attempts
-    adapt_begin<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, h->d_actl, h->a_chunks, u, uc, uf, tab);
+    adapt_begin<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, h->d_actl, h->a_chunks,
+                                                       static_cast<cplx<R> *>(h->state), static_cast<cplx<R> *>(h->a_uc),
+                                                       static_cast<cplx<R> *>(h->a_uf),
+                                                       static_cast<Phasor<R> *>(h->a_tab));
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(h->stream));
     bool spent = false;

@@ -90,6 +90,8 @@ struct AdaptState {
     double z;            // position reached by the accepted steps
     double end;          // where the propagation ends
     double dz;           // step of the next attempt (already cut at the end)
+    double tol;          // error tolerance of the run
+    int max_attempts;    // attempt budget of the run (accepted + rejected)
     int status;          // 0 running, 1 reached the end, 2 attempt budget spent
     int last;            // the next attempt ends at `end`
     int pend;            // the last attempt was kept: the coarse and fine
@@ -814,32 +816,44 @@ __global__ __launch_bounds__(kThreads) void adapt_error(const InstDesc *inst, co
     }
 }
 
-// One thread per instance. mode 0 starts a run from z0 over `length` with
-// step dz0; mode 1 takes the decision of the attempt just made. Both then
-// prepare the next attempt: stop at the end or when the budget is spent,
-// else cut a step that would pass the end.
+// One wave per instance (lane 0 decides). mode 0 starts a run from z0 over
+// `length` with step dz0; mode 1 takes the decision of the attempt just made.
+// Both then prepare the next attempt: stop at the end or when the budget is
+// spent, else cut a step that would pass the end.
 __global__ __launch_bounds__(kThreads) void adapt_control(AdaptState *ctl, int n_inst, int chunks,
                                                           const double *part, int mode, double z0, double length,
                                                           double dz0, double tol, int max_attempts)
 {
-    for (int ii = threadIdx.x; ii < n_inst; ii += kThreads) {
+    const int lane = threadIdx.x & 63;
+    for (int ii = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); ii < n_inst; ii += gridDim.x * (kThreads / 64)) {
+        // error sums of the attempt: lane-strided partials, then a fixed shuffle tree
+        double num = 0.0, den = 0.0;
+        if (mode == 1)
+            for (int c = lane; c < chunks; c += 64) {
+                num += part[2 * (static_cast<long long>(ii) * chunks + c)];
+                den += part[2 * (static_cast<long long>(ii) * chunks + c) + 1];
+            }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            num += __shfl_down(num, o, 64);
+            den += __shfl_down(den, o, 64);
+        }
+        if (lane != 0) continue;
         AdaptState st = ctl[ii];
         if (mode == 0) {
             st.z = z0;
             st.end = z0 + length;
             st.dz = dz0;
+            st.tol = tol;
+            st.max_attempts = max_attempts;
             st.status = 0;
             st.last = 0;
             st.pend = 0;
             st.accepted = 0;
             st.rejected = 0;
         } else if (st.status == 0) {
-            double num = 0.0, den = 0.0;
-            for (int c = 0; c < chunks; ++c) {
-                num += part[2 * (static_cast<long long>(ii) * chunks + c)];
-                den += part[2 * (static_cast<long long>(ii) * chunks + c) + 1];
-            }
             const double dd = sqrt(num / den);
+            const double tol = st.tol;
             if (dd > 2.0 * tol) {
                 st.dz *= 0.5;
                 st.rejected += 1;
@@ -857,7 +871,7 @@ __global__ __launch_bounds__(kThreads) void adapt_control(AdaptState *ctl, int n
         if (st.status == 0) {
             if (!(st.z < st.end)) {
                 st.status = 1;
-            } else if (st.accepted + st.rejected >= max_attempts) {
+            } else if (st.accepted + st.rejected >= st.max_attempts) {
                 st.status = 2;
             } else {
                 const double rest = st.end - st.z;

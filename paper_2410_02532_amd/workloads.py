@@ -249,6 +249,25 @@ def config(name, **over):
                              fields=f[:2].copy(), pump_in=pump))
         return dict(name=name, instances=inst, nz=over.get("nz", 100),
                     n_rt=over.get("n_rt", windows), precision="f32")
+    if name == "adaptive_pulsed":      # uneven-Nt single-pass amplifiers under the adaptive step
+        count = over.get("count", 32)
+        rng = np.random.Generator(np.random.PCG64(5))
+        sizes = 1 << rng.integers(over.get("min_log2", 12), over.get("max_log2", 16) + 1,
+                                  size=count)
+        gains = rng.uniform(3.0, 8.0, size=count)        # small-signal gain-length at the peak
+        dks = rng.uniform(-1.0, 1.0, size=count)
+        inst = []
+        for b in range(count):
+            nt = int(sizes[b])
+            cr = crystal(nt, b3=500.0, dk_per_mm=float(dks[b]))
+            peak = gains[b] / (cr["length_mm"] * math.sqrt(coupling_product(cr)))
+            pump = gaussian_pulse(nt, peak, 2.0)
+            f = initial_fields(nt, pump, 4000 + b)
+            f[1] += gaussian_pulse(nt, 1e-3 * peak, 1.0)
+            inst.append(dict(crystal=cr, cavity=cavity(resonant=(0, 0, 0), refl=(0.0, 0.0, 0.0)),
+                             fields=f, pump_in=pump))
+        return dict(name=name, instances=inst, nz=over.get("nz", 100), n_rt=0,
+                    tol=over.get("tol", 1e-5), precision="f32")
     if name == "dro_large":            # DRO, Nt = 2^20, GDD +-2000 fs^2, EOM 1 rad at 1/T
         nt = over.get("nt", 1 << 20)
         count = over.get("count", 16)

@@ -157,3 +157,23 @@ def test_adaptive_edges():
         with pytest.raises(B.OpoError) as e:
             h.ssfm_propagate_adaptive(1.0, 1e-6, 0.1)
         assert e.value.code == B.OPO_EINVAL
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_adaptive_graph_replay_equals_plain_launches(precision):
+    """The attempt replayed from a graph (many replays, host read-backs between chunks,
+    and a second call on the same handle) equals plain launches bit for bit."""
+    say("adaptive graph vs plain %s" % precision)
+    insts = [_inst(2048, 21), _inst(4096, 23, dk=-0.3), _inst(1024, 25, nf=2)]
+    L, tol, dz0 = 2.0, 1e-5, 0.05
+    out = {}
+    for g in (True, False):
+        with B.Opo(insts, 40, precision=precision, use_graph=g) as h:
+            r1 = h.ssfm_propagate_adaptive(1.2, tol, dz0)
+            r2 = h.ssfm_propagate_adaptive(L - 1.2, tol, dz0)
+            out[g] = (r1, r2, [h.get_fields(i) for i in range(len(insts))])
+    for k in range(2):
+        for q in range(3):
+            assert np.array_equal(out[True][k][q], out[False][k][q])
+    for i in range(len(insts)):
+        assert np.array_equal(out[True][2][i], out[False][2][i])
