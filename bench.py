@@ -283,7 +283,7 @@ def main():
         var["f32_ns_pulsed"] = {"value": pt_steps_per_rt(ws) * n / d, "round_trips": n,
                                 "ms_per_step": d * 1e3 / n, "instances": len(ws["instances"]),
                                 "nt": ws["instances"][0]["crystal"]["nt"], "record": True}
-        # adaptive step: 32 uneven-Nt single-pass amplifiers (gain-length 3-8, 2 ps pump,
+        # adaptive step: 128 uneven-Nt single-pass amplifiers (gain-length 3-8, 2 ps pump,
         # mismatch spread), each choosing its own steps, tol 1e-5
         ws = W.config("adaptive_pulsed")
         var["f32_adaptive_pulsed"] = adaptive_run(ws)

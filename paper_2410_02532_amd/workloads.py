@@ -250,7 +250,7 @@ def config(name, **over):
         return dict(name=name, instances=inst, nz=over.get("nz", 100),
                     n_rt=over.get("n_rt", windows), precision="f32")
     if name == "adaptive_pulsed":      # uneven-Nt single-pass amplifiers under the adaptive step
-        count = over.get("count", 32)
+        count = over.get("count", 128)
         rng = np.random.Generator(np.random.PCG64(5))
         sizes = 1 << rng.integers(over.get("min_log2", 12), over.get("max_log2", 16) + 1,
                                   size=count)
