@@ -229,6 +229,17 @@ int opo_set_fields(opo_t *h, int32_t inst, int32_t field, const double *in);
 int opo_get_energy_history(opo_t *h, int32_t inst, double *out, int32_t capacity,
                            int32_t *rows);
 
+/* Output power history [W], the same rows as the energy history: each field's
+ * mean intensity over the window as it leaves the crystal,
+ * I_x = n_x eps0 c E_x / (2 nt) (Sec. 2.1 field units, V/m), times the
+ * effective beam area area_m2 [m^2], times 1 - R_x for a resonant field (the
+ * part its output coupler passes; Eq. 6) or 1 for a non-resonant field (it
+ * leaves the cavity whole). The idler entry is 0 for two waves. For an
+ * on-axis Gaussian peak I = 2P / (pi w0^2), area_m2 = pi w0^2 / 2. OPO_EINVAL
+ * for area_m2 <= 0 or a bad instance, capacity or pointer. */
+int opo_get_power_history(opo_t *h, int32_t inst, double area_m2, double *out, int32_t capacity,
+                          int32_t *rows);
+
 /* Field `field` of instance `inst` as it left the crystal in round trip rt
  * (counted from opo_init; rt < record_rt and < the round trips run so far),
  * nt interleaved complex128 time samples, from the record of the record_rt

@@ -191,6 +191,7 @@ struct opo_s {
     int a_chunks = 0;
     hipGraphExec_t a_graph = nullptr;   // one attempt, replayed (reads everything from the device)
     std::vector<double> t_window;    // T of every instance [ps]
+    std::vector<double> out_scale;   // [instance][3] output power per unit area and energy, see opo_get_power_history
     // profile option: event pairs of the launches since the last collection
     bool profile = false;
     std::vector<hipEvent_t> events;
@@ -982,6 +983,16 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     hipError_t le = hipGetLastError();
     if (le != hipSuccess) return bail(fail(OPO_EDEVICE, std::string("init: ") + hipGetErrorString(le)));
     for (int i = 0; i < n; ++i) h->t_window.push_back(f[i].t_window_ps);
+    // output power of field x per unit beam area from its recorded energy E_x:
+    // mean intensity n_x eps0 c E_x / (2 nt), times 1 - R_x through the output
+    // coupler of a resonant field, or whole for a non-resonant one
+    constexpr double kEps0 = 8.8541878128e-12, kC0 = 299792458.0;
+    for (int i = 0; i < n; ++i)
+        for (int x = 0; x < 3; ++x) {
+            const bool used = x < nfields(f[i]);
+            const double t = k[i].resonant[x] ? 1.0 - k[i].refl[x] : 1.0;
+            h->out_scale.push_back(used ? t * 0.5 * f[i].n[x] * kEps0 * kC0 / f[i].nt : 0.0);
+        }
     {
         std::lock_guard<std::mutex> lk(g_live_mu);
         g_live.insert(h);
@@ -1383,6 +1394,22 @@ int opo_get_energy_history(opo_t *h, int32_t inst, double *out, int32_t capacity
     for (int r = 0; r < m; ++r)
         for (int x = 0; x < 3; ++x)
             out[3 * r + x] = h->hist[(static_cast<size_t>(r) * h->n_inst + inst) * 3 + x];
+    if (rows) *rows = h->hist_rows;
+    return OPO_OK;
+}
+
+int opo_get_power_history(opo_t *h, int32_t inst, double area_m2, double *out, int32_t capacity, int32_t *rows)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    if (inst < 0 || inst >= h->n_inst || capacity < 0 || (capacity > 0 && !out) || !(area_m2 > 0.0) ||
+        !std::isfinite(area_m2))
+        return fail(OPO_EINVAL, "bad instance, capacity, output pointer or area");
+    const int m = std::min(capacity, h->hist_rows);
+    for (int r = 0; r < m; ++r)
+        for (int x = 0; x < 3; ++x)
+            out[3 * r + x] = h->hist[(static_cast<size_t>(r) * h->n_inst + inst) * 3 + x] *
+                             h->out_scale[3 * static_cast<size_t>(inst) + x] * area_m2;
     if (rows) *rows = h->hist_rows;
     return OPO_OK;
 }

@@ -20,6 +20,7 @@ STATUS = {0: "OPO_OK", -1: "OPO_EINVAL", -2: "OPO_ENOMEM", -3: "OPO_EDEVICE",
 EXPORTS = ("opo_state_bytes", "opo_init", "opo_init_batch", "ssfm_propagate", "ssfm_propagate_adaptive",
            "cavity_roundtrip",
            "opo_sync", "opo_get_fields", "opo_set_fields", "opo_get_energy_history",
+           "opo_get_power_history",
            "opo_get_record", "opo_get_grid", "opo_kernel_times", "opo_info", "opo_destroy",
            "opo_last_error")
 KERNEL_CLASSES = ("column_pass", "row_pass", "energy_reduce", "mixed_pass")
@@ -91,6 +92,7 @@ def load():
     lib.opo_set_fields.argtypes = [P, I, I, P]
     lib.opo_get_energy_history.argtypes = [P, I, P, I, ctypes.POINTER(I)]
     lib.opo_get_record.argtypes = [P, I, I, I, P]
+    lib.opo_get_power_history.argtypes = [P, I, D, P, I, ctypes.POINTER(I)]
     lib.opo_get_grid.argtypes = [P, I, P, P]
     lib.opo_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(D)]
     lib.opo_kernel_times.argtypes = [P, P, P]
@@ -100,6 +102,7 @@ def load():
     for name in ("opo_init", "opo_init_batch", "ssfm_propagate", "ssfm_propagate_adaptive",
                  "cavity_roundtrip", "opo_sync",
                  "opo_get_fields", "opo_set_fields", "opo_get_energy_history", "opo_get_record",
+                 "opo_get_power_history",
                  "opo_get_grid",
                  "opo_kernel_times", "opo_info", "opo_destroy"):
         getattr(lib, name).restype = ctypes.c_int
@@ -270,6 +273,16 @@ class Opo:
         if rows.value:
             _check(self._lib.opo_get_energy_history(self.h, inst, out.ctypes.data, rows.value,
                                                     ctypes.byref(rows)))
+        return out
+
+    def power_history(self, area_m2, inst=0):
+        """Output powers [W] per round trip (rows, 3) over an effective beam area [m^2]."""
+        rows = ctypes.c_int32()
+        _check(self._lib.opo_get_power_history(self.h, inst, float(area_m2), None, 0, ctypes.byref(rows)))
+        out = np.zeros((rows.value, 3))
+        if rows.value:
+            _check(self._lib.opo_get_power_history(self.h, inst, float(area_m2), out.ctypes.data, rows.value,
+                                                   ctypes.byref(rows)))
         return out
 
     def record(self, rt, inst=0):
