@@ -97,6 +97,8 @@
 typedef double complex cplx;
 
 #define ORA_PI 3.14159265358979323846
+#define ORA_CBRT2 1.25992104989487316477   /* 2^(1/3), the nearest double (libm cbrt is not
+                                             always correctly rounded) */
 
 typedef struct {
     int nt;                /* time points, a power of two                 */
@@ -530,7 +532,7 @@ int ora_propagate_adaptive(const ora_crystal *c, cplx *a, double z0, double leng
     if (c->order != 2) return -2;
     const size_t n = (size_t)c->nf * (size_t)c->nt;
     cplx *uc = malloc(sizeof(cplx) * n), *uf = malloc(sizeof(cplx) * n);
-    const double grow = cbrt(2.0), end = z0 + length;
+    const double grow = ORA_CBRT2, end = z0 + length;
     double z = z0, dz = dz0;
     int rc = 0;
     while (z < end) {
