@@ -206,6 +206,8 @@ def main():
                     help="skip the single-instance FP32 and FP64 lines")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--adaptive-only", action="store_true",
+                    help="only the adaptive-step variant (adaptive_pulsed), one JSON line")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -220,6 +222,9 @@ def main():
         return 1
     if args.copy_calibration:
         copy_calibration()
+    if args.adaptive_only:
+        print(json.dumps(adaptive_run(W.config("adaptive_pulsed"))), flush=True)
+        return 0
 
     w = W.config(args.workload, precision=args.precision) if args.workload == "sro_cw" else \
         W.config(args.workload)

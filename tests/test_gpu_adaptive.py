@@ -177,3 +177,51 @@ def test_adaptive_graph_replay_equals_plain_launches(precision):
             assert np.array_equal(out[True][k][q], out[False][k][q])
     for i in range(len(insts)):
         assert np.array_equal(out[True][2][i], out[False][2][i])
+
+
+def test_adaptive_smallest_grids_and_zero_fields():
+    """nt = 2 and 4 (one-point columns and rows) beside a regular instance, and an
+    all-zero instance: its d is 0/0, never above a threshold, so every attempt is kept
+    at dz0 and the count is ceil(L / dz0), as in the oracle."""
+    say("adaptive tiny and zero")
+
+    def cw(nt):
+        cr = W.crystal(nt, t_window_ps=20.0, deff=40.0, dk_per_mm=0.8)
+        a = np.stack([np.full(nt, 2e6 + 0j), np.full(nt, 2e5 + 1e4j), np.full(nt, 1e4 + 0j)])
+        return dict(crystal=cr, cavity=W.cavity(), fields=a, pump_in=a[0].copy())
+
+    zero = dict(crystal=W.crystal(64, t_window_ps=20.0, deff=40.0), cavity=W.cavity(),
+                fields=np.zeros((3, 64), complex), pump_in=np.zeros(64, complex))
+    insts = [cw(2), cw(4), _inst(1024, 31), zero]
+    L, tol, dz0 = 2.0, 1e-7, 0.3
+    with B.Opo(insts, 40, precision="f64") as h:
+        acc, rej, z = h.ssfm_propagate_adaptive(L, tol, dz0)
+        got = [h.get_fields(i) for i in range(len(insts))]
+    assert (acc[3], rej[3]) == (int(np.ceil(L / dz0)), 0)
+    assert np.all(got[3] == 0) and np.all(z == L)
+    for i, ins in enumerate(insts[:3]):
+        ref, ra, rr = _oracle(ins, L, tol, dz0)
+        assert (acc[i], rej[i]) == (ra, rr), i
+        for x in range(3):
+            assert rel_l2(got[i][x], ref[x]) <= TOL["f64"], (i, x)
+
+
+def test_adaptive_largest_fp32_grid():
+    """2^20 points per field (256-point columns, 4096-point rows) in FP32 against the
+    oracle over a short length."""
+    say("adaptive 2^20 f32")
+    nt = 1 << 20
+    cr = W.crystal(nt, t_window_ps=100.0, deff=40.0, dk_per_mm=0.8, b3=500.0)
+    t = W.time_grid(nt, 100.0)
+    a = np.stack([3e6 * np.exp(-t * t / 8.0) + 0j,
+                  2e5 * np.exp(-(t - 1.0) ** 2 / 2.0) + W.noise(nt, 1e3, 3), W.noise(nt, 1e4, 4)])
+    ins = dict(crystal=cr, cavity=W.cavity(), fields=a, pump_in=a[0].copy())
+    L, tol, dz0 = 0.5, 1e-4, 0.05
+    ref, ra, rr = _oracle(ins, L, tol, dz0)
+    with B.Opo([ins], 40, precision="f32") as h:
+        acc, rej, _ = h.ssfm_propagate_adaptive(L, tol, dz0)
+        got = h.get_fields()
+    same = (acc[0], rej[0]) == (ra, rr)
+    assert same or (abs(acc[0] - ra) <= 2 and abs(rej[0] - rr) <= 2)
+    for x in range(3):
+        assert rel_l2(got[x], ref[x]) <= (TOL["f32"] if same else 10 * tol), x
