@@ -197,8 +197,8 @@ int ssfm_propagate(opo_t *h, int32_t nz, double dz);
  * each, or NULL) receive each instance's counts and the z it reached. Returns
  * OPO_ESTEPS if an instance spent its budget first (its fields then hold the
  * last accepted step, at z_end); the handle's z advances by length_mm. The
- * first call allocates two state-sized copies and per-instance propagator
- * tables (4x the state in FP32, 2x in FP64) kept until opo_destroy.
+ * first call allocates two state-sized copies and a per-instance propagator
+ * table (2x the state in FP32, 1x in FP64) kept until opo_destroy.
  * Synchronizes the stream. */
 int ssfm_propagate_adaptive(opo_t *h, double length_mm, double tol, double dz0, int32_t max_attempts,
                             int32_t *accepted, int32_t *rejected, double *z_end);

@@ -1068,17 +1068,21 @@ template <typename R> static void enqueue_attempt(opo_t *h)
     a.adapt = h->d_actl;
     a.disp = tab;
     adapt_begin<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, h->d_actl, h->a_chunks, u, uc, uf, tab);
-    a.state = uc;                 // one step of dz
+    a.state = uc;                 // one step of dz, from u
     a.adapt_scale = 1.0;
+    a.src = u;
     launch_a<R>(h, a, A_RK_THIS | A_FWD, 0);
+    a.src = nullptr;
     launch_b<R>(h, a, B_DISP, 0, 0);
     launch_a<R>(h, a, A_INV | A_RK_PREV, 1);
-    a.state = uf;                 // two steps of dz/2
+    a.state = uf;                 // two steps of dz/2, from u
     a.adapt_scale = 0.5;
+    a.src = u;
     launch_a<R>(h, a, A_RK_THIS | A_FWD, 0);
-    launch_b<R>(h, a, B_DISP, 0, 1);
+    a.src = nullptr;
+    launch_b<R>(h, a, B_DISP, 0, 0);
     launch_a<R>(h, a, A_INV | A_RK_PREV | A_RK_THIS | A_FWD, 1);
-    launch_b<R>(h, a, B_DISP, 1, 1);
+    launch_b<R>(h, a, B_DISP, 1, 0);
     launch_a<R>(h, a, A_INV | A_RK_PREV, 2);
     adapt_error<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, h->d_actl, h->a_chunks, uc, uf, h->d_apart);
     adapt_control<<<(h->n_inst + kThreads / 64 - 1) / (kThreads / 64), kThreads, 0, h->stream>>>(h->d_actl, h->n_inst, h->a_chunks, h->d_apart, 1, 0.0, 0.0, 0.0,
@@ -1103,7 +1107,7 @@ static int adaptive_impl(opo_t *h, double length, double tol, double dz0, int ma
         if (static_cast<long long>(h->a_chunks) * h->n_inst > 2147483647LL)
             return fail(OPO_EINVAL, "too many instances for the adaptive step");
         if (hipMalloc(&h->a_uc, h->state_bytes) != hipSuccess || hipMalloc(&h->a_uf, h->state_bytes) != hipSuccess ||
-            hipMalloc(&h->a_tab, 2 * n_elem * sizeof(Phasor<R>)) != hipSuccess ||
+            hipMalloc(&h->a_tab, n_elem * sizeof(Phasor<R>)) != hipSuccess ||
             hipMalloc(&h->d_actl, h->n_inst * sizeof(AdaptState)) != hipSuccess ||
             hipMalloc(&h->d_apart, 2 * sizeof(double) * h->a_chunks * h->n_inst) != hipSuccess)
             return fail(OPO_ENOMEM, "hipMalloc of the adaptive-step buffers failed");

@@ -125,10 +125,12 @@ template <typename R> struct StepArgs {
     // the first half of this step at zf_this with size hf_this (z from zbase)
     double zf_prev, hf_prev, zf_this, hf_this;
     // adaptive step: per-instance z and dz (instances not running skip their
-    // tiles), the launch's step is adapt_scale * dz, and the propagator tables
-    // are per instance at 2 * off (coarse dz, then fine dz/2)
+    // tiles), the launch's step is adapt_scale * dz, the propagator table of
+    // dz/2 is per instance at off (a row pass of dz applies it twice), and a
+    // column launch may load its fields from src instead of state
     const AdaptState *adapt;
     double adapt_scale;
+    const cplx<R> *src;
 };
 
 // ---------------------------------------------------------------- shapes --
@@ -447,6 +449,7 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     const int j1 = (tile - d.tile_a0) * COLS + c;
     const bool act = j1 < n1;
     V *g = a.state + d.off + j1;
+    const V *gs = (a.src ? a.src : a.state) + d.off + j1;
 
     double dz = a.dz_arg > 0.0 ? a.dz_arg : d.length_mm / a.nz;
     double zb = a.dz_arg > 0.0 ? a.zbase : 0.0;
@@ -469,7 +472,7 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int m = 0; m < PF; ++m)
-            v[f][m] = act ? g[static_cast<long long>(f) * nt + static_cast<long long>(n1) * (t + m * T)]
+            v[f][m] = act ? gs[static_cast<long long>(f) * nt + static_cast<long long>(n1) * (t + m * T)]
                           : mk<V>(R(0), R(0));
 
     int base[NF];
@@ -623,12 +626,18 @@ __device__ __forceinline__ void row_tile(const StepArgs<R> &a, const InstDesc &d
     if (!(flags & B_FWD_ONLY)) {
         if (flags & B_DISP) {
             // H_f(k)/nt from the instance's table, laid out like the rows
-            const long long toff = a.adapt ? 2LL * d.off : d.disp_off;
+            const long long toff = a.adapt ? d.off : d.disp_off;
             const Phasor<R> *h = a.disp + toff + static_cast<long long>(a.disp_sel * d.nf + f) * nt +
                                  static_cast<long long>(N) * k2 + t;
 #pragma unroll
             for (int m = 0; m < PF; ++m)
                 if (act) v[0][m] = pmul(v[0][m], h[m * T]);
+            if (a.adapt && a.adapt_scale == 1.0) {   // adaptive coarse step: H(dz)/nt = (H(dz/2)/nt)^2 nt
+                const R scale = static_cast<R>(nt);      // a power of two: exact
+#pragma unroll
+                for (int m = 0; m < PF; ++m)
+                    if (act) v[0][m] = cscale(pmul(v[0][m], h[m * T]), scale);
+            }
         } else if (flags & B_GDD) {
             const double inv_nt = 1.0 / nt;
             if ((d.gdd_mask >> f) & 1) {
@@ -758,11 +767,13 @@ constexpr double kAdaptGrow = 1.25992104989487316477;   // 2^(1/3), the nearest 
 constexpr double kAdaptSlack = 1.0 + 1e-9;   // a step that stops within 1e-9 dz of the end goes to it
 
 // Fields of the attempt: the extrapolation of the step kept by the previous
-// attempt (also for instances that have just stopped), copied to u_c and u_f
-// for a running instance, with its coarse and fine propagator tables.
+// attempt (also for instances that have just stopped), and for a running
+// instance its propagator table of dz/2. The first column launch of the
+// coarse and of the fine step then loads u and stores into u_c or u_f.
 template <typename R>
 __global__ __launch_bounds__(kThreads) void adapt_begin(const InstDesc *inst, const AdaptState *ctl, int chunks,
-                                                        cplx<R> *u, cplx<R> *uc, cplx<R> *uf, Phasor<R> *tab)
+                                                        cplx<R> *u, const cplx<R> *uc, const cplx<R> *uf,
+                                                        Phasor<R> *tab)
 {
     using V = cplx<R>;
     const int ii = blockIdx.x / chunks, ch = blockIdx.x - ii * chunks;
@@ -774,20 +785,11 @@ __global__ __launch_bounds__(kThreads) void adapt_begin(const InstDesc *inst, co
     for (long long q = ch * static_cast<long long>(kThreads) + threadIdx.x; q < n;
          q += static_cast<long long>(chunks) * kThreads) {
         const long long j = d.off + q;
-        V x;
         if (st.pend) {
             const V f = uf[j], c = uc[j];
-            x = mk<V>((R(4) * f.x - c.x) / R(3), (R(4) * f.y - c.y) / R(3));
-            u[j] = x;
-        } else {
-            x = u[j];
+            u[j] = mk<V>((R(4) * f.x - c.x) / R(3), (R(4) * f.y - c.y) / R(3));
         }
-        if (run) {
-            uc[j] = x;
-            uf[j] = x;
-            tab[2 * d.off + q] = propagator<R>(d, q, st.dz);
-            tab[2 * d.off + n + q] = propagator<R>(d, q, 0.5 * st.dz);
-        }
+        if (run) tab[j] = propagator<R>(d, q, 0.5 * st.dz);
     }
 }
 
