@@ -236,36 +236,63 @@ __device__ __forceinline__ void coupling_tile(const InstDesc &d, double z_prev, 
     }
 }
 
-// k * t; with IMAG the coefficient is known to be purely imaginary (dk = 0,
-// so e^{+-i dk z} = 1 and k = i kappa h/2) and its zero real part is skipped.
-template <bool IMAG, typename V> __device__ __forceinline__ V kmul(V k, V t)
-{
-    if constexpr (IMAG) return mk<V>(-k.y * t.y, k.y * t.x);
-    else return cmul(k, t);
-}
-
-// Right-hand side of Eqs. 2-4 (nonlinear part) times h/2.
-template <bool IMAG, typename V>
+// Right-hand side of Eqs. 2-4 (nonlinear part) times h/2, with the stage's
+// coupling coefficients k (i kappa e^{-+i dk z} h/2).
+template <typename V>
 __device__ __forceinline__ void cwe_rhs(const V (&k)[3], V ap, V as, V ai, V &fp, V &fs, V &fi)
 {
-    fp = kmul<IMAG>(k[0], cmul(as, ai));
-    fs = kmul<IMAG>(k[1], cmulc(ap, ai));
-    fi = kmul<IMAG>(k[2], cmulc(ap, as));
+    fp = cmul(k[0], cmul(as, ai));
+    fs = cmul(k[1], cmulc(ap, ai));
+    fi = cmul(k[2], cmulc(ap, as));
+}
+
+// y + i c t for a real c (one FMA per component).
+template <typename V, typename S> __device__ __forceinline__ V add_ic(V y, S c, V t)
+{
+    return mk<V>(y.x - c * t.y, y.y + c * t.x);
+}
+
+// RK4 with dk = 0: every stage coefficient is the same i c_x (c_x = kappa_x h/2),
+// so the stage slopes are i c_x t_n with t_n the bare products, and c_x moves
+// into the FMAs that form the stage inputs and the final combination.
+template <typename R>
+__device__ __forceinline__ void rk4_point_imag(const cplx<R> (&c)[3][3], cplx<R> &ap, cplx<R> &as, cplx<R> &ai)
+{
+    using V = cplx<R>;
+    const R cp = c[0][0].y, cs = c[0][1].y, ci = c[0][2].y;
+    const R two = R(2), third = R(1) / R(3);
+    const V p1 = cmul(as, ai), s1 = cmulc(ap, ai), i1 = cmulc(ap, as);
+    V bp = add_ic(ap, cp, p1), bs = add_ic(as, cs, s1), bi = add_ic(ai, ci, i1);
+    const V p2 = cmul(bs, bi), s2 = cmulc(bp, bi), i2 = cmulc(bp, bs);
+    bp = add_ic(ap, cp, p2);
+    bs = add_ic(as, cs, s2);
+    bi = add_ic(ai, ci, i2);
+    const V p3 = cmul(bs, bi), s3 = cmulc(bp, bi), i3 = cmulc(bp, bs);
+    bp = add_ic(ap, two * cp, p3);
+    bs = add_ic(as, two * cs, s3);
+    bi = add_ic(ai, two * ci, i3);
+    const V p4 = cmul(bs, bi), s4 = cmulc(bp, bi), i4 = cmulc(bp, bs);
+    auto comb = [&](V t1, V t2, V t3, V t4) {
+        return mk<V>(t1.x + two * (t2.x + t3.x) + t4.x, t1.y + two * (t2.y + t3.y) + t4.y);
+    };
+    ap = add_ic(ap, third * cp, comb(p1, p2, p3, p4));
+    as = add_ic(as, third * cs, comb(s1, s2, s3, s4));
+    ai = add_ic(ai, third * ci, comb(i1, i2, i3, i4));
 }
 
 // Classical coupled RK4 over one step h with stage coefficients at z0, z0+h/2,
 // z0+h (each pre-scaled by h/2, so y + h/2 k_n becomes y + k'_n).
-template <typename R, bool IMAG>
+template <typename R>
 __device__ __forceinline__ void rk4_point(const cplx<R> (&c)[3][3], cplx<R> &ap, cplx<R> &as,
                                           cplx<R> &ai)
 {
     using V = cplx<R>;
     V p1, s1, i1, p2, s2, i2, p3, s3, i3, p4, s4, i4;
-    cwe_rhs<IMAG>(c[0], ap, as, ai, p1, s1, i1);
-    cwe_rhs<IMAG>(c[1], cadd(ap, p1), cadd(as, s1), cadd(ai, i1), p2, s2, i2);
-    cwe_rhs<IMAG>(c[1], cadd(ap, p2), cadd(as, s2), cadd(ai, i2), p3, s3, i3);
+    cwe_rhs(c[0], ap, as, ai, p1, s1, i1);
+    cwe_rhs(c[1], cadd(ap, p1), cadd(as, s1), cadd(ai, i1), p2, s2, i2);
+    cwe_rhs(c[1], cadd(ap, p2), cadd(as, s2), cadd(ai, i2), p3, s3, i3);
     const R two = R(2);
-    cwe_rhs<IMAG>(c[2], mk<V>(ap.x + two * p3.x, ap.y + two * p3.y), mk<V>(as.x + two * s3.x, as.y + two * s3.y),
+    cwe_rhs(c[2], mk<V>(ap.x + two * p3.x, ap.y + two * p3.y), mk<V>(as.x + two * s3.x, as.y + two * s3.y),
                   mk<V>(ai.x + two * i3.x, ai.y + two * i3.y), p4, s4, i4);
     const R third = R(1) / R(3);
     ap = mk<V>(ap.x + third * (p1.x + two * (p2.x + p3.x) + p4.x),
@@ -278,23 +305,45 @@ __device__ __forceinline__ void rk4_point(const cplx<R> (&c)[3][3], cplx<R> &ap,
 
 // The two-wave right-hand side times h/2: (i kappa_p2 A_s^2 e^{-i dk z},
 // i kappa_s A_p A_s^* e^{+i dk z}) with the same stage coefficients.
-template <bool IMAG, typename V>
+template <typename V>
 __device__ __forceinline__ void cwe2_rhs(const V (&k)[3], V ap, V as, V &fp, V &fs)
 {
-    fp = kmul<IMAG>(k[0], cmul(as, as));
-    fs = kmul<IMAG>(k[1], cmulc(ap, as));
+    fp = cmul(k[0], cmul(as, as));
+    fs = cmul(k[1], cmulc(ap, as));
 }
 
-template <typename R, bool IMAG>
+// Two-wave RK4 with dk = 0, factored like rk4_point_imag.
+template <typename R>
+__device__ __forceinline__ void rk4_point2_imag(const cplx<R> (&c)[3][3], cplx<R> &ap, cplx<R> &as)
+{
+    using V = cplx<R>;
+    const R cp = c[0][0].y, cs = c[0][1].y;
+    const R two = R(2), third = R(1) / R(3);
+    const V p1 = cmul(as, as), s1 = cmulc(ap, as);
+    V bp = add_ic(ap, cp, p1), bs = add_ic(as, cs, s1);
+    const V p2 = cmul(bs, bs), s2 = cmulc(bp, bs);
+    bp = add_ic(ap, cp, p2);
+    bs = add_ic(as, cs, s2);
+    const V p3 = cmul(bs, bs), s3 = cmulc(bp, bs);
+    bp = add_ic(ap, two * cp, p3);
+    bs = add_ic(as, two * cs, s3);
+    const V p4 = cmul(bs, bs), s4 = cmulc(bp, bs);
+    ap = add_ic(ap, third * cp,
+                mk<V>(p1.x + two * (p2.x + p3.x) + p4.x, p1.y + two * (p2.y + p3.y) + p4.y));
+    as = add_ic(as, third * cs,
+                mk<V>(s1.x + two * (s2.x + s3.x) + s4.x, s1.y + two * (s2.y + s3.y) + s4.y));
+}
+
+template <typename R>
 __device__ __forceinline__ void rk4_point2(const cplx<R> (&c)[3][3], cplx<R> &ap, cplx<R> &as)
 {
     using V = cplx<R>;
     V p1, s1, p2, s2, p3, s3, p4, s4;
-    cwe2_rhs<IMAG>(c[0], ap, as, p1, s1);
-    cwe2_rhs<IMAG>(c[1], cadd(ap, p1), cadd(as, s1), p2, s2);
-    cwe2_rhs<IMAG>(c[1], cadd(ap, p2), cadd(as, s2), p3, s3);
+    cwe2_rhs(c[0], ap, as, p1, s1);
+    cwe2_rhs(c[1], cadd(ap, p1), cadd(as, s1), p2, s2);
+    cwe2_rhs(c[1], cadd(ap, p2), cadd(as, s2), p3, s3);
     const R two = R(2);
-    cwe2_rhs<IMAG>(c[2], mk<V>(ap.x + two * p3.x, ap.y + two * p3.y), mk<V>(as.x + two * s3.x, as.y + two * s3.y),
+    cwe2_rhs(c[2], mk<V>(ap.x + two * p3.x, ap.y + two * p3.y), mk<V>(as.x + two * s3.x, as.y + two * s3.y),
                    p4, s4);
     const R third = R(1) / R(3);
     ap = mk<V>(ap.x + third * (p1.x + two * (p2.x + p3.x) + p4.x),
@@ -332,9 +381,9 @@ __device__ __forceinline__ void rk4_kerr(const cplx<R> (&c)[3][3], const R (&g)[
     const V y[3] = {y0, y1, y2};
     V k[4][3], t[3];
     auto slope = [&](int st, const V (&in)[3], V (&out)[3]) {
-        if constexpr (NF == 3) cwe_rhs<false>(c[st], in[0], in[1], in[2], out[0], out[1], out[2]);
+        if constexpr (NF == 3) cwe_rhs(c[st], in[0], in[1], in[2], out[0], out[1], out[2]);
         else {
-            cwe2_rhs<false>(c[st], in[0], in[1], out[0], out[1]);
+            cwe2_rhs(c[st], in[0], in[1], out[0], out[1]);
             out[2] = mk<V>(R(0), R(0));
         }
         kerr_add<R, NF>(g, in, out);
@@ -371,11 +420,11 @@ __device__ __forceinline__ void rk4_fields(const Coupling<R> &cp, int which, boo
         return;
     }
     if constexpr (NF == 3) {
-        if (imag) rk4_point<R, true>(c, y0, y1, y2);
-        else rk4_point<R, false>(c, y0, y1, y2);
+        if (imag) rk4_point_imag<R>(c, y0, y1, y2);
+        else rk4_point<R>(c, y0, y1, y2);
     } else {
-        if (imag) rk4_point2<R, true>(c, y0, y1);
-        else rk4_point2<R, false>(c, y0, y1);
+        if (imag) rk4_point2_imag<R>(c, y0, y1);
+        else rk4_point2<R>(c, y0, y1);
     }
 }
 
