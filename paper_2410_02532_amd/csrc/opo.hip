@@ -1109,8 +1109,16 @@ static int adaptive_impl(opo_t *h, double length, double tol, double dz0, int ma
         if (hipMalloc(&h->a_uc, h->state_bytes) != hipSuccess || hipMalloc(&h->a_uf, h->state_bytes) != hipSuccess ||
             hipMalloc(&h->a_tab, n_elem * sizeof(Phasor<R>)) != hipSuccess ||
             hipMalloc(&h->d_actl, h->n_inst * sizeof(AdaptState)) != hipSuccess ||
-            hipMalloc(&h->d_apart, 2 * sizeof(double) * h->a_chunks * h->n_inst) != hipSuccess)
+            hipMalloc(&h->d_apart, 2 * sizeof(double) * h->a_chunks * h->n_inst) != hipSuccess) {
+            // all or none: a later call allocates again
+            void **bufs[] = {&h->a_uc, &h->a_uf, &h->a_tab, reinterpret_cast<void **>(&h->d_actl),
+                             reinterpret_cast<void **>(&h->d_apart)};
+            for (void **b : bufs) {
+                if (*b) (void)hipFree(*b);
+                *b = nullptr;
+            }
             return fail(OPO_ENOMEM, "hipMalloc of the adaptive-step buffers failed");
+        }
     }
     const int blocks = h->a_chunks * h->n_inst;
     if (h->use_graph && !h->a_graph) {
