@@ -74,8 +74,8 @@ def timed_roundtrips(h, n_rt):
     return e0.elapsed_time(e1) / 1e3, wall
 
 
-def run_gpu(w, steps, warmup, precision):
-    with B.from_workload(w, precision=precision) as h:
+def run_gpu(w, steps, warmup, precision, **kw):
+    with B.from_workload(w, precision=precision, **kw) as h:
         if warmup:
             h.cavity_roundtrip(warmup)
         dev_s, wall_s = timed_roundtrips(h, steps)
@@ -259,6 +259,11 @@ def main():
             d, _ = run_gpu(ws, n, 10, prec)
             var["%s_single_sro_cw_2^14" % prec] = {"value": pt_steps_per_rt(ws) * n / d,
                                                   "round_trips": n, "ms_per_step": d * 1e3 / n}
+            # the same with columns of 32 (col_log2 option): twice the column
+            # workgroups, each with half the work, for an instance alone
+            d, _ = run_gpu(ws, n, 10, prec, col_log2=5)
+            var["%s_single_sro_cw_2^14_col32" % prec] = {"value": pt_steps_per_rt(ws) * n / d,
+                                                        "round_trips": n, "ms_per_step": d * 1e3 / n}
         # the synchronously pumped OPO at its largest grid, FP32 and FP64
         for prec in ("f32", "f64"):
             ws = W.config("sync_pumped", nt=1 << 18, precision=prec)

@@ -129,8 +129,16 @@ typedef struct {
                                kept alive until opo_destroy; NULL = the library
                                allocates it                                       */
     uint64_t state_bytes;   /* size of *state                                     */
-    int32_t tile_a;         /* points per column-pass tile (0 = autotuned)        */
-    int32_t tile_b;         /* points per row-pass tile (0 = autotuned)           */
+    int32_t col_log2;       /* four-step split nt = n1 * n2 (Sec. 2.2 FFTs): log2 n2
+                               for instances of nt > 2^10, 0 = automatic (n2 = 64
+                               from 2^13 up to the longest rows). 5 (n2 = 32)
+                               gives a single instance of 2^13..2^17 twice the
+                               column workgroups with half the work each: faster
+                               alone (2^14 FP32 +15 %), slower in a large batch.
+                               Clamped to n2 <= n1 and n1 <= 4096 (FP32) or 2048
+                               (FP64). Results differ from another split by
+                               rounding only. 0 or 4..8, else OPO_EINVAL          */
+    int32_t reserved0;      /* must be 0                                          */
     int32_t use_graph;      /* 1 = replay each round trip from a hipGraph
                                (default), -1 = plain launches                     */
     int32_t profile;        /* 1 = bracket every kernel launch with a pair of

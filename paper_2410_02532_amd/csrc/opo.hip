@@ -49,12 +49,15 @@ static int ilog2(long long v)
 // Four-step split nt = n1 * n2: balanced up to 2^12, then columns of 64
 // (short column transforms keep three fields of 128-byte column groups in
 // registers) and rows up to the longest row kernel, then longer columns.
-static Plan make_plan(int nt, int precision)
+// col_log2 > 0 asks for columns of 2^col_log2 instead (for nt > 2^10, and
+// never shorter than the longest rows allow, nor longer than balanced).
+static Plan make_plan(int nt, int precision, int col_log2)
 {
     Plan p;
     const int l = ilog2(nt);
     const int max_ln1 = precision == OPO_F64 ? kMaxLog2N1<double> : kMaxLog2N1<float>;
-    if (l <= 12) p.log2n2 = l / 2;
+    if (col_log2 > 0 && l > 10) p.log2n2 = std::max(std::min(col_log2, l / 2), l - max_ln1);
+    else if (l <= 12) p.log2n2 = l / 2;
     else p.log2n2 = std::max(6, l - max_ln1);
     p.log2n1 = l - p.log2n2;
     p.cols = precision == OPO_F64 ? col_cols<double>(p.log2n2) : col_cols<float>(p.log2n2);
@@ -652,6 +655,9 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     if (opt.record_rt < 0) return fail(OPO_EINVAL, "record_rt must be >= 0");
     const int K = opt.n_crystals > 1 ? opt.n_crystals : 1;
     if (opt.n_crystals < 0) return fail(OPO_EINVAL, "n_crystals must be >= 0");
+    if (opt.col_log2 != 0 && (opt.col_log2 < 4 || opt.col_log2 > kMaxLog2N2))
+        return fail(OPO_EINVAL, "col_log2 must be 0 or 4.." + std::to_string(kMaxLog2N2));
+    if (opt.reserved0 != 0) return fail(OPO_EINVAL, "reserved option fields must be 0");
     if (opt.split_order != 0 && opt.split_order != 2 && opt.split_order != 4)
         return fail(OPO_EINVAL, "split_order must be 2, 4 or 0 (= 2)");
     // the longest symmetrized step of the fourth-order composition is |b| dz
@@ -703,7 +709,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     for (int i = 0; i < n; ++i) {
         InstDesc &d = h->inst[i];
         std::memset(&d, 0, sizeof(d));
-        const Plan p = make_plan(f[i].nt, opt.precision);
+        const Plan p = make_plan(f[i].nt, opt.precision, opt.col_log2);
         d.nt = f[i].nt;
         d.log2nt = ilog2(d.nt);
         d.n1 = 1 << p.log2n1;

@@ -53,8 +53,8 @@ class CavityT(ctypes.Structure):
 class OptionsT(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("state", ctypes.c_void_p),
-                ("state_bytes", ctypes.c_uint64), ("tile_a", ctypes.c_int32),
-                ("tile_b", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("state_bytes", ctypes.c_uint64), ("col_log2", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("record_rt", ctypes.c_int32),
                 ("n_crystals", ctypes.c_int32), ("split_order", ctypes.c_int32)]
 
@@ -200,7 +200,7 @@ class Opo:
     runs on a torch stream (default priority) created for the handle.
     """
 
-    def __init__(self, instances, nz, precision="f32", device=0, tile_a=0, tile_b=0,
+    def __init__(self, instances, nz, precision="f32", device=0, col_log2=0,
                  use_graph=True, profile=False, record_rt=0, split_order=2):
         import torch
         lib = load()
@@ -218,7 +218,7 @@ class Opo:
         opt = OptionsT(precision=self.precision, device=device,
                        stream=ctypes.c_void_p(self._stream.cuda_stream),
                        state=ctypes.c_void_p(self._state.data_ptr()), state_bytes=nbytes,
-                       tile_a=int(tile_a), tile_b=int(tile_b), use_graph=1 if use_graph else -1,
+                       col_log2=int(col_log2), use_graph=1 if use_graph else -1,
                        profile=1 if profile else 0, record_rt=int(record_rt),
                        n_crystals=len(nz) if np.ndim(nz) else 1, split_order=int(split_order))
         h = ctypes.c_void_p()
