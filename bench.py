@@ -264,6 +264,11 @@ def main():
             d, _ = run_gpu(ws, n, 10, prec, col_log2=5)
             var["%s_single_sro_cw_2^14_col32" % prec] = {"value": pt_steps_per_rt(ws) * n / d,
                                                         "round_trips": n, "ms_per_step": d * 1e3 / n}
+        # the headline workload in FP64 (complex128 throughout)
+        n = 50
+        d, _ = run_gpu(w, n, 3, "f64")
+        var["f64_%s" % args.workload] = {"value": pt_steps_per_rt(w) * n / d, "round_trips": n,
+                                         "ms_per_step": d * 1e3 / n}
         # the synchronously pumped OPO at its largest grid, FP32 and FP64
         for prec in ("f32", "f64"):
             ws = W.config("sync_pumped", nt=1 << 18, precision=prec)
