@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -169,7 +170,8 @@ struct opo_s {
     int *d_map[2] = {nullptr, nullptr};  // workgroup -> tile maps of the two mixed launches
     int map_len[2] = {0, 0};
     int *d_tile_a = nullptr, *d_tile_b = nullptr;
-    void *d_tw = nullptr, *d_tw4 = nullptr;
+    void *d_tw = nullptr;
+    void *d_w4tab = nullptr;         // four-step twiddle tables, one per distinct (nt, n1)
     void *d_disp = nullptr;          // linear-propagator tables, one per distinct crystal/grid
     std::vector<int> disp_owner;     // instance whose parameters define each table
     double disp_mode = -1.0;         // step the tables hold: > 0 explicit dz, 0 = L/nz, < 0 none
@@ -336,17 +338,6 @@ static int validate(int n, int K, const opo_fields_t *f, const opo_crystal_t *c,
     return OPO_OK;
 }
 
-static void build_twiddles_rows(std::vector<double> &re, std::vector<double> &im, long long n,
-                                long long count, double scale)
-{
-    // e^{-2 pi i q scale / n}, q < count, in FP64
-    for (long long q = 0; q < count; ++q) {
-        const double a = kTwoPi * static_cast<double>(q) * scale / static_cast<double>(n);
-        re.push_back(std::cos(a));
-        im.push_back(-std::sin(a));
-    }
-}
-
 // Unit-modulus factors computed in FP64, stored as Phasor<R> (compensated
 // FP32 pairs, or FP64).
 template <typename R> static void upload_phasors(void *dst, const std::vector<double> &re,
@@ -356,16 +347,6 @@ template <typename R> static void upload_phasors(void *dst, const std::vector<do
     for (size_t i = 0; i < re.size(); ++i)
         buf[i] = make_phasor<R>(re[i], im[i]);
     (void)hipMemcpyAsync(dst, buf.data(), buf.size() * sizeof(Phasor<R>), hipMemcpyHostToDevice, st);
-    (void)hipStreamSynchronize(st);
-}
-
-static void upload_double2(void *dst, const std::vector<double> &re, const std::vector<double> &im,
-                           hipStream_t st)
-{
-    std::vector<double2> buf(re.size());
-    for (size_t i = 0; i < re.size(); ++i)
-        buf[i] = make_double2(re[i], im[i]);
-    (void)hipMemcpyAsync(dst, buf.data(), buf.size() * sizeof(double2), hipMemcpyHostToDevice, st);
     (void)hipStreamSynchronize(st);
 }
 
@@ -400,7 +381,7 @@ static void release(opo_t *h)
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->a_graph) (void)hipGraphExecDestroy(h->a_graph);
     if (h->own_state && h->state) (void)hipFree(h->state);
-    void *bufs[] = {h->pump, h->d_inst, h->d_tile_a, h->d_tile_b, h->d_tw, h->d_tw4, h->d_disp, h->d_map[0], h->d_map[1],
+    void *bufs[] = {h->d_w4tab, h->pump, h->d_inst, h->d_tile_a, h->d_tile_b, h->d_tw, h->d_disp, h->d_map[0], h->d_map[1],
                     h->d_partial, h->d_hist, h->d_counter, h->scratch, h->d_record,
                     h->a_uc, h->a_uf, h->a_tab, h->d_actl, h->d_apart};
     for (void *b : bufs)
@@ -422,7 +403,7 @@ template <typename R> static StepArgs<R> base_args(opo_t *h, void *state)
     a.state = static_cast<cplx<R> *>(state);
     a.pump = static_cast<const cplx<R> *>(h->pump);
     a.tw = static_cast<const Phasor<R> *>(h->d_tw);
-    a.tw4 = static_cast<const double2 *>(h->d_tw4);
+    a.w4tab = static_cast<const Phasor<R> *>(h->d_w4tab);
     a.disp = static_cast<const Phasor<R> *>(h->d_disp);
     a.partial = h->d_partial;
     a.counter = h->d_counter;
@@ -702,7 +683,8 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     // ---- plan and per-instance descriptors
     const uint64_t need = opo_state_bytes(n, f, opt.precision);
     long long off = 0, pump_elems = 0;
-    std::vector<double> t4re, t4im;
+    std::map<std::pair<int, int>, long long> w4map;   // (log2 nt, log2 n1) -> four-step table offset
+    long long w4_elems = 0;
     std::vector<int> tile_a_inst, tile_b_inst;
     size_t max_a = 0, max_b = 0;
     h->inst.resize(n);
@@ -739,12 +721,16 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
             static_cast<long long>(d.n1) * d.n2 != d.nt || d.cols < 1 || d.rows < 1)
             return bail(fail(OPO_EINVAL, "internal: tile plan out of bounds for nt " + std::to_string(d.nt)));
 
-        // four-step twiddles e^{-2 pi i m/nt}: low table m < 2^b, high table (m >> b) << b
-        const int bits = (d.log2nt + 1) / 2;
-        d.tw4_off = static_cast<int>(t4re.size());
-        d.tw4_bits = bits;
-        build_twiddles_rows(t4re, t4im, d.nt, 1LL << bits, 1.0);
-        build_twiddles_rows(t4re, t4im, d.nt, d.nt >> bits, static_cast<double>(1LL << bits));
+        // four-step twiddles W_nt^{j1 k2}: one table per distinct (nt, n1)
+        {
+            const std::pair<int, int> key(d.log2nt, d.log2n1);
+            auto it = w4map.find(key);
+            if (it == w4map.end()) {
+                it = w4map.emplace(key, w4_elems).first;
+                w4_elems += d.nt;
+            }
+            d.w4_off = it->second;
+        }
 
         int res = 0, gdd = 0, eom = 0;
         for (int x = 0; x < d.nf; ++x) {
@@ -925,7 +911,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         hipMalloc(reinterpret_cast<void **>(&h->d_tile_a), h->tiles_a * sizeof(int)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_tile_b), h->tiles_b * sizeof(int)) != hipSuccess ||
         hipMalloc(&h->d_tw, static_cast<size_t>(kTwEntries) * 16) != hipSuccess ||
-        hipMalloc(&h->d_tw4, t4re.size() * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&h->d_w4tab, static_cast<size_t>(w4_elems) * 16) != hipSuccess ||
         hipMalloc(&h->d_disp, static_cast<size_t>(disp_elems) * 16) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_partial), h->tiles_a * 3 * sizeof(double)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_hist),
@@ -963,7 +949,22 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         return bail(fail(OPO_EDEVICE, "upload of the instance tables failed"));
     if (opt.precision == OPO_F64) upload_phasors<double>(h->d_tw, twre, twim, st);
     else upload_phasors<float>(h->d_tw, twre, twim, st);
-    upload_double2(h->d_tw4, t4re, t4im, st);
+    {
+        // W_nt^{j1 k2} = e^{-2 pi i (j1 k2 mod nt)/nt} in FP64 at k2 * n1 + j1
+        std::vector<double> wre(static_cast<size_t>(w4_elems)), wim(static_cast<size_t>(w4_elems));
+        for (const auto &e : w4map) {
+            const long long nt4 = 1LL << e.first.first, n1 = 1LL << e.first.second, n2 = nt4 / n1;
+            for (long long k2 = 0; k2 < n2; ++k2)
+                for (long long j1 = 0; j1 < n1; ++j1) {
+                    const long long m = (j1 * k2) & (nt4 - 1);
+                    const double a = kTwoPi * static_cast<double>(m) / static_cast<double>(nt4);
+                    wre[e.second + k2 * n1 + j1] = std::cos(a);
+                    wim[e.second + k2 * n1 + j1] = -std::sin(a);
+                }
+        }
+        if (opt.precision == OPO_F64) upload_phasors<double>(h->d_w4tab, wre, wim, st);
+        else upload_phasors<float>(h->d_w4tab, wre, wim, st);
+    }
     std::vector<double> zeros;
     for (int i = 0; i < n; ++i) {
         const InstDesc &d = h->inst[i];

@@ -39,6 +39,7 @@ struct InstDesc {
     long long off;        // element offset of the pump field; signal +nt, idler +2nt
     long long pump_off;   // element offset of the input-pump samples, -1 = constant pump
     long long disp_off;   // offset of the instance's linear-propagator table (nf nt entries)
+    long long w4_off;     // offset of the four-step twiddle table W_nt^{j1 k2} at k2 * n1 + j1
     int nt, log2nt;
     int n1, log2n1;       // row length (contiguous)
     int n2, log2n2;       // column length (stride n1)
@@ -46,8 +47,6 @@ struct InstDesc {
     int rows;             // rows per row tile
     int tile_a0, tiles_a; // first column tile of the instance, and count
     int tile_b0, tiles_b; // first row tile, and count (nf fields x row blocks)
-    int tw4_off;          // four-step twiddle tables: 2^tw4_bits low entries, then high
-    int tw4_bits;
     int res_mask, gdd_mask, eom_mask;
     int nf;               // coupled waves: 3 (p, s, i) or 2 (p, s; degenerate)
     int pump_windows;     // > 1: round trip m reads window m of the input pump (zero after)
@@ -105,7 +104,7 @@ template <typename R> struct StepArgs {
     cplx<R> *state;
     const cplx<R> *pump;
     const Phasor<R> *tw;      // butterfly twiddles e^{-2 pi i q/kTwL}
-    const double2 *tw4;       // four-step twiddle tables (FP64)
+    const Phasor<R> *w4tab;   // four-step twiddles W_nt^{j1 k2} per (nt, n1), from FP64
     const Phasor<R> *disp;    // linear-propagator tables H_x(k)/nt in row-pass order
     double *partial;          // [column tiles][3] energy partial sums
     const int *counter;       // [0] energy-history slot, [1] round trips completed
@@ -191,17 +190,6 @@ __device__ __forceinline__ double2 unit_rev(double rho)
     double sn, cs;
     sincospi(2.0 * (rho - rint(rho)), &sn, &cs);
     return make_double2(cs, sn);
-}
-
-// Four-step twiddle W_nt^m = e^{-2 pi i m/nt}: the product of a low and a
-// high FP64 table entry, formed in FP64.
-template <typename R>
-__device__ __forceinline__ Phasor<R> twiddle4(const double2 *__restrict__ t, int bits, unsigned m)
-{
-    const double2 lo = t[m & ((1u << bits) - 1u)];
-    const double2 hi = t[(1u << bits) + (m >> bits)];
-    const double2 w = cmul(hi, lo);
-    return make_phasor<R>(w.x, w.y);
 }
 
 // Coupling coefficients of the RK4 stages of the two half-steps a column tile
@@ -511,11 +499,13 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
         coupling_tile<R>(d, zb + a.zf_prev * dz, a.hf_prev * dz, zb + a.zf_this * dz, a.hf_this * dz, cpl);
 
     V v[NF][PF];
-    // four-step twiddle W_nt^{j1 k2} of sample m; formed where it is used (before
-    // the inverse and after the forward column FFT) rather than held in registers
-    const double2 *t4 = a.tw4 + d.tw4_off;
+    // four-step twiddle W_nt^{j1 k2} of sample m, read from the table of this
+    // (nt, n1) where it is used (before the inverse and after the forward
+    // column FFT) rather than held in registers; the COLS columns of a row of
+    // the table are adjacent, and the tables of a batch stay in L2
+    const Phasor<R> *w4t = a.w4tab + d.w4_off + j1;
     auto w4 = [&](int m) {
-        return twiddle4<R>(t4, d.tw4_bits, (static_cast<unsigned>(j1) * static_cast<unsigned>(t + m * T)) & (nt - 1));
+        return act ? w4t[static_cast<long long>(t + m * T) * n1] : make_phasor<R>(1.0, 0.0);
     };
 #pragma unroll
     for (int f = 0; f < NF; ++f)
