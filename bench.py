@@ -264,6 +264,17 @@ def main():
             d, _ = run_gpu(ws, n, 10, prec, col_log2=5)
             var["%s_single_sro_cw_2^14_col32" % prec] = {"value": pt_steps_per_rt(ws) * n / d,
                                                         "round_trips": n, "ms_per_step": d * 1e3 / n}
+        # the headline workload one instance at a time (a handle per instance, same
+        # kernels): the batching gain on the same work
+        if "instances" in w:
+            n, tot_s, pts = 3, 0.0, 0
+            for ins in w["instances"]:
+                one = dict(ins, nz=w["nz"])
+                d, _ = run_gpu(one, n, 1, args.precision)
+                tot_s += d
+                pts += ins["crystal"]["nt"] * w["nz"] * n
+            var["%s_%s_one_at_a_time" % (args.precision, args.workload)] = {
+                "value": pts / tot_s, "round_trips": n, "ms_per_step": tot_s * 1e3 / n}
         # the headline workload in FP64 (complex128 throughout)
         n = 50
         d, _ = run_gpu(w, n, 3, "f64")
