@@ -225,3 +225,26 @@ def test_adaptive_largest_fp32_grid():
     assert same or (abs(acc[0] - ra) <= 2 and abs(rej[0] - rr) <= 2)
     for x in range(3):
         assert rel_l2(got[x], ref[x]) <= (TOL["f32"] if same else 10 * tol), x
+
+
+def test_adaptive_pulsed_workload_sampled():
+    """The benchmark's adaptive workload as the benchmark runs it (128 uneven instances,
+    FP32, tol 1e-5, dz0 = L/100): the three smallest instances and the first of the
+    largest against the oracle, and every instance reaches the end."""
+    say("adaptive workload, sampled")
+    w = W.config("adaptive_pulsed")
+    insts = w["instances"]
+    L = insts[0]["crystal"]["length_mm"]
+    with B.Opo(insts, w["nz"], precision="f32") as h:
+        acc, rej, z = h.ssfm_propagate_adaptive(L, w["tol"], L / w["nz"])
+        order = sorted(range(len(insts)), key=lambda i: (insts[i]["crystal"]["nt"], i))
+        big = max(insts[i]["crystal"]["nt"] for i in order)
+        picks = order[:3] + [next(i for i in order if insts[i]["crystal"]["nt"] == big)]
+        got = {i: h.get_fields(i) for i in picks}
+    assert np.all(z == L)
+    for i in picks:
+        ref, ra, rr = oracle.propagate_adaptive(insts[i]["crystal"], insts[i]["fields"], L, w["tol"], L / w["nz"])
+        same = (acc[i], rej[i]) == (ra, rr)
+        assert same or (abs(acc[i] - ra) <= 2 and abs(rej[i] - rr) <= 2), (i, (acc[i], rej[i]), (ra, rr))
+        for x in range(3):
+            assert rel_l2(got[i][x], ref[x]) <= (TOL["f32"] if same else 10 * w["tol"]), (i, x)
