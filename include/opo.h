@@ -215,9 +215,15 @@ int ssfm_propagate_adaptive(opo_t *h, double length_mm, double tol, double dz0, 
  * pump and zero non-resonant signal/idler, one pass of crystal.nz steps with
  * dz = L/nz from z = 0, record sum_j |A_x(t_j)|^2 in FP64, apply GDD, the
  * mirror factor sqrt(R_x) e^{i delta_x} of Eq. 6, then the EOM. Appends n_rt
- * rows to the energy history. Returns OPO_ENONFINITE (after finishing the
- * call) if any recorded energy is not finite; opo_history_length and the
- * history tell where. Synchronizes the stream at the end. */
+ * rows to the energy history. Synchronizes the stream at the end.
+ * Non-finite results (the too-large step of Sec. 2.4 ends in NaN): if a round
+ * trip m records an energy that is not finite, or ends with a field value that
+ * is not finite, the call stops there and returns OPO_ENONFINITE. Round trip m
+ * appends no row and no later round trip runs; the fields, z and the count of
+ * round trips completed (which selects the next input-pump window and record
+ * slot) are those after round trip m - 1, the last finite one (the fields m
+ * started from). opo_get_progress and the message name m. The library keeps
+ * that starting state in a device buffer of opo_state_bytes() bytes. */
 int cavity_roundtrip(opo_t *h, int32_t n_rt);
 
 /* Wait for all work queued on the handle's stream. */
@@ -226,9 +232,29 @@ int opo_sync(opo_t *h);
 /* Copy field `field` (0 p, 1 s, 2 i; < n_fields) of instance `inst` to/from host memory
  * as nt interleaved complex128 values. domain 0 = time samples A(t_j);
  * domain 1 (get only) = unnormalized DFT sum_j A(t_j) e^{-2 pi i jk/nt} in
- * natural bin order. set also resets the instance's z to 0. */
+ * natural bin order. set also resets the handle's z to 0 (opo_set_progress
+ * sets it). Stored at the handle's precision: complex64 values read with get
+ * and set back are restored bit for bit. */
 int opo_get_fields(opo_t *h, int32_t inst, int32_t field, int32_t domain, double *out);
 int opo_set_fields(opo_t *h, int32_t inst, int32_t field, const double *in);
+
+/* Checkpoint and resume (the per-round-trip save of Sec. 4.1). A run is
+ * resumed bit for bit by a handle created with the same inputs and options:
+ * set every field with opo_set_fields, then opo_set_progress with what
+ * opo_get_progress and the energy histories gave.
+ * get: *rt_done = round trips completed since opo_init (= energy-history
+ * rows), *z_mm = the z that the next ssfm_propagate continues from (either
+ * pointer may be NULL).
+ * set: the handle continues as after rt_done round trips: the next round trip
+ * reads input-pump window rt_done (pump_windows > 1) and record slot rt_done,
+ * the energy history becomes the rt_done rows of `history` (rt_done x
+ * instances x 3 doubles, round-trip major, as the per-instance histories
+ * stacked; NULL only for rt_done = 0), and z becomes z_mm (finite, >= 0).
+ * The record (record_rt option) is not restored: slots of round trips run
+ * before the restore read as zeros. OPO_EINVAL for bad arguments. Waits for
+ * the handle's stream. */
+int opo_get_progress(opo_t *h, int32_t *rt_done, double *z_mm);
+int opo_set_progress(opo_t *h, int32_t rt_done, double z_mm, const double *history);
 
 /* Energy history: out receives min(capacity, rows) rows of 3 doubles
  * sum_j |A_x(t_j)|^2 (p, s, i; the idler entry is 0 for two waves) after each

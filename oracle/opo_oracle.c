@@ -521,7 +521,9 @@ void ora_roundtrips(const ora_crystal *c, const ora_cavity *cav, cplx *a,
  * (4 u_f - u_c)/3 is accepted, z advances by dz, and dz is divided by 2^(1/3)
  * if d > tol, multiplied by it if d < tol/2. A step that would pass the end,
  * or stop short of it by less than 1e-9 dz, is cut (or stretched) to end
- * there, and z is then set to the end itself. Second-order steps
+ * there, and z is then set to the end itself. A d that is not a number
+ * rejects the attempt, except for fields that are zero everywhere (0/0),
+ * which keep it with dz unchanged. Second-order steps
  * only (the extrapolation weights assume them). Returns 0; -1 when max_steps
  * attempts (accepted and rejected) do not reach the end; -2 for order != 2. */
 int ora_propagate_adaptive(const ora_crystal *c, cplx *a, double z0, double length, double tol, double dz0,
@@ -553,8 +555,13 @@ int ora_propagate_adaptive(const ora_crystal *c, cplx *a, double z0, double leng
             num += creal(e) * creal(e) + cimag(e) * cimag(e);
             den += creal(uf[i]) * creal(uf[i]) + cimag(uf[i]) * cimag(uf[i]);
         }
+        /* d is undefined (0/0) for fields that are zero everywhere: the attempt
+         * is kept with dz unchanged. Any other d that is not a number (a step
+         * that overflowed, non-finite fields) rejects the attempt like a too
+         * large error; the attempt budget ends a run that never recovers. */
+        const int zero = num == 0.0 && den == 0.0;
         const double d = sqrt(num / den);
-        if (d > 2.0 * tol) {
+        if (!zero && !(d <= 2.0 * tol)) {
             dz *= 0.5;
             ++*rejected;
             continue;

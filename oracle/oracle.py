@@ -279,10 +279,11 @@ def roundtrips_multi(crystals, nzs, cavity, a, pump_in, n_rt, record=False):
     return a, e, rec
 
 
-def propagate_adaptive(crystal, a, length, tol, dz0, max_steps=100000, z0=0.0):
+def propagate_adaptive(crystal, a, length, tol, dz0, max_steps=100000, z0=0.0, budget_ok=False):
     """Propagation from z0 over `length` mm with the local-error adaptive step (second-order
     steps only). Returns (fields, accepted steps, rejected steps); raises RuntimeError when
-    max_steps attempts do not reach the end."""
+    max_steps attempts do not reach the end, unless budget_ok (the fields then hold the last
+    accepted step)."""
     a = _fields(a, crystal)
     acc, rej = ctypes.c_int(), ctypes.c_int()
     rc = _load().ora_propagate_adaptive(ctypes.byref(Crystal.from_dict(crystal)), _ptr(a), float(z0),
@@ -290,6 +291,6 @@ def propagate_adaptive(crystal, a, length, tol, dz0, max_steps=100000, z0=0.0):
                                         ctypes.byref(acc), ctypes.byref(rej))
     if rc == -2:
         raise ValueError("the adaptive step needs second-order steps (order 2)")
-    if rc != 0:
+    if rc != 0 and not budget_ok:
         raise RuntimeError("adaptive propagation did not reach the end in %d attempts" % max_steps)
     return a, acc.value, rej.value

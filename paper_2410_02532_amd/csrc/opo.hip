@@ -2,7 +2,7 @@
 // planning (four-step split, tile shapes, FP64 tables), launch sequences of a
 // crystal pass and of a cavity round trip, hipGraph replay, read-back.
 #include "opo.h"
-#include "ssfm_kernels.h"
+#include "kernel_list.h"
 
 #include <algorithm>
 #include <cmath>
@@ -17,6 +17,9 @@
 
 namespace opo {
 
+// the kernel instantiations live in the k_*.hip units
+OPO_ALL_KERNELS(extern template)
+
 static thread_local std::string g_err;
 
 static int fail(int code, const std::string &msg)
@@ -30,6 +33,13 @@ static int fail(int code, const std::string &msg)
         hipError_t e_ = (expr);                                                                  \
         if (e_ != hipSuccess)                                                                    \
             return fail(OPO_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+    } while (0)
+
+// Propagates a failed HIP call out of a function that returns hipError_t.
+#define HIP_RET(expr)                                                                            \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess) return e_;                                                         \
     } while (0)
 
 static constexpr int kHistChunk = 1024;   // round trips buffered on the device per read-back
@@ -177,7 +187,9 @@ struct opo_s {
     double disp_mode = -1.0;         // step the tables hold: > 0 explicit dz, 0 = L/nz, < 0 none
     double *d_partial = nullptr;
     double *d_hist = nullptr;
-    int *d_counter = nullptr;        // [0] history slot in the chunk, [1] round trips completed
+    int *d_counter = nullptr;        // [0] history slot in the chunk, [1] round trips completed,
+                                     // [2] stop flag, [3] non-finite boundary value (ssfm_kernels.h)
+    void *d_snap = nullptr;          // state at the start of the current round trip
     void *d_record = nullptr;        // [record_cap][state] fields leaving the crystal per round trip
     int record_cap = 0;
     size_t lds_a = 0, lds_b = 0;
@@ -340,24 +352,26 @@ static int validate(int n, int K, const opo_fields_t *f, const opo_crystal_t *c,
 
 // Unit-modulus factors computed in FP64, stored as Phasor<R> (compensated
 // FP32 pairs, or FP64).
-template <typename R> static void upload_phasors(void *dst, const std::vector<double> &re,
-                                                 const std::vector<double> &im, hipStream_t st)
+template <typename R> static hipError_t upload_phasors(void *dst, const std::vector<double> &re,
+                                                       const std::vector<double> &im, hipStream_t st)
 {
     std::vector<Phasor<R>> buf(re.size());
     for (size_t i = 0; i < re.size(); ++i)
         buf[i] = make_phasor<R>(re[i], im[i]);
-    (void)hipMemcpyAsync(dst, buf.data(), buf.size() * sizeof(Phasor<R>), hipMemcpyHostToDevice, st);
-    (void)hipStreamSynchronize(st);
+    hipError_t e = hipMemcpyAsync(dst, buf.data(), buf.size() * sizeof(Phasor<R>), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);   // buf is released on return
 }
 
-template <typename R> static void host_to_state(void *dst, const double *src, long long count,
-                                                hipStream_t st)
+template <typename R> static hipError_t host_to_state(void *dst, const double *src, long long count,
+                                                      hipStream_t st)
 {
     std::vector<R> buf(2 * count);
     for (long long i = 0; i < 2 * count; ++i)
         buf[i] = static_cast<R>(src[i]);
-    (void)hipMemcpyAsync(dst, buf.data(), buf.size() * sizeof(R), hipMemcpyHostToDevice, st);
-    (void)hipStreamSynchronize(st);
+    hipError_t e = hipMemcpyAsync(dst, buf.data(), buf.size() * sizeof(R), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(st);
 }
 
 template <typename R> static hipError_t state_to_host(double *dst, const void *src, long long count,
@@ -382,7 +396,7 @@ static void release(opo_t *h)
     if (h->a_graph) (void)hipGraphExecDestroy(h->a_graph);
     if (h->own_state && h->state) (void)hipFree(h->state);
     void *bufs[] = {h->d_w4tab, h->pump, h->d_inst, h->d_tile_a, h->d_tile_b, h->d_tw, h->d_disp, h->d_map[0], h->d_map[1],
-                    h->d_partial, h->d_hist, h->d_counter, h->scratch, h->d_record,
+                    h->d_partial, h->d_hist, h->d_counter, h->scratch, h->d_record, h->d_snap,
                     h->a_uc, h->a_uf, h->a_tab, h->d_actl, h->d_apart};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -430,26 +444,31 @@ static void substep(const opo_t *h, int i, double &z, double &tau, int &sel)
 }
 
 // profile option: open an event pair around the next launch of class k
-static void prof_begin(opo_t *h, int k)
+static hipError_t prof_begin(opo_t *h, int k)
 {
-    if (!h->profile) return;
+    if (!h->profile) return hipSuccess;
     if (h->ev_used + 2 > h->events.size()) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        (void)hipEventCreate(&e0);
-        (void)hipEventCreate(&e1);
+        HIP_RET(hipEventCreate(&e0));
+        hipError_t e = hipEventCreate(&e1);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(e0);   // already failing: the first error is the one reported
+            return e;
+        }
         h->events.push_back(e0);
         h->events.push_back(e1);
         h->ev_class.push_back(k);
     }
     h->ev_class[h->ev_used / 2] = k;
-    (void)hipEventRecord(h->events[h->ev_used], h->stream);
+    return hipEventRecord(h->events[h->ev_used], h->stream);
 }
 
-static void prof_end(opo_t *h)
+static hipError_t prof_end(opo_t *h)
 {
-    if (!h->profile) return;
-    (void)hipEventRecord(h->events[h->ev_used + 1], h->stream);
+    if (!h->profile) return hipSuccess;
+    HIP_RET(hipEventRecord(h->events[h->ev_used + 1], h->stream));
     h->ev_used += 2;
+    return hipSuccess;
 }
 
 // profile option: wait for the recorded launches and add up the times of the
@@ -486,42 +505,43 @@ template <typename R> static void set_half_steps(const opo_t *h, StepArgs<R> &a,
     a.hf_this = 0.5 * tau;
 }
 
-template <typename R> static void launch_a(opo_t *h, StepArgs<R> a, int flags, int step, int half = -1)
+template <typename R> static hipError_t launch_a(opo_t *h, StepArgs<R> a, int flags, int step, int half = -1)
 {
     a.tile_inst = h->d_tile_a;
     a.flags = flags;
     set_half_steps<R>(h, a, step);
-    prof_begin(h, OPO_K_COLUMN);
+    HIP_RET(prof_begin(h, OPO_K_COLUMN));
     for (const Group &g : h->groups_a) {
         if (half >= 0 && g.half != half) continue;
         a.tile0 = g.tile0;
         a.tile_count = g.count;
         void *args[] = {&a};
-        (void)hipLaunchKernel(column_fn<R>(g.ln, g.nf), dim3(g.count), dim3(kThreads), args, h->lds_a, h->stream);
+        HIP_RET(hipLaunchKernel(column_fn<R>(g.ln, g.nf), dim3(g.count), dim3(kThreads), args, h->lds_a,
+                                h->stream));
     }
-    prof_end(h);
+    return prof_end(h);
 }
 
-template <typename R> static void launch_b(opo_t *h, StepArgs<R> a, int flags, int step = 0, int sel = -1)
+template <typename R> static hipError_t launch_b(opo_t *h, StepArgs<R> a, int flags, int step = 0, int sel = -1)
 {
     a.tile_inst = h->d_tile_b;
     a.flags = flags;
     double z, tau;
     substep(h, step, z, tau, a.disp_sel);
     if (sel >= 0) a.disp_sel = sel;
-    prof_begin(h, OPO_K_ROW);
+    HIP_RET(prof_begin(h, OPO_K_ROW));
     for (const Group &g : h->groups_b) {
         a.tile0 = g.tile0;
         a.tile_count = g.count;
         void *args[] = {&a};
-        (void)hipLaunchKernel(row_fn<R>(g.ln), dim3(g.count), dim3(kThreads), args, h->lds_b, h->stream);
+        HIP_RET(hipLaunchKernel(row_fn<R>(g.ln), dim3(g.count), dim3(kThreads), args, h->lds_b, h->stream));
     }
-    prof_end(h);
+    return prof_end(h);
 }
 
 // Column tiles of half `ch` (flags, step) with the row tiles (B_DISP) of the
 // other half, in one launch.
-template <typename R> static void launch_mixed(opo_t *h, StepArgs<R> a, int ch, int cflags, int step)
+template <typename R> static hipError_t launch_mixed(opo_t *h, StepArgs<R> a, int ch, int cflags, int step)
 {
     const Group &gc = h->groups_a[ch], &gr = h->groups_b[1 - ch];
     StepArgs<R> ac = a, ar = a;
@@ -541,43 +561,45 @@ template <typename R> static void launch_mixed(opo_t *h, StepArgs<R> a, int ch, 
     ar.tile0 = gr.tile0;
     ar.tile_count = gr.count;
     void *args[] = {&ac, &ar};
-    prof_begin(h, OPO_K_MIXED);
-    (void)hipLaunchKernel(mixed_fn<R>(gc.ln, gr.ln, gc.nf), dim3(h->map_len[ch]), dim3(kThreads), args,
-                          std::max(h->lds_a, h->lds_b), h->stream);
-    prof_end(h);
+    HIP_RET(prof_begin(h, OPO_K_MIXED));
+    HIP_RET(hipLaunchKernel(mixed_fn<R>(gc.ln, gr.ln, gc.nf), dim3(h->map_len[ch]), dim3(kThreads), args,
+                            std::max(h->lds_a, h->lds_b), h->stream));
+    return prof_end(h);
 }
 
 // One crystal pass of nz steps. `first` flags are OR-ed into the opening
 // column pass (refresh), `last` into the closing one (energy, mirror, EOM).
 template <typename R>
-static void enqueue_pass(opo_t *h, StepArgs<R> a, int nz_steps, int first, int last)
+static hipError_t enqueue_pass(opo_t *h, StepArgs<R> a, int nz_steps, int first, int last)
 {
     const int nz = nz_steps * (h->order == 4 ? 3 : 1);   // symmetrized steps of the pass
     if (h->mixed) {
         // half 0 runs one launch ahead of half 1
         const int mid = A_INV | A_RK_PREV | A_RK_THIS | A_FWD;
-        launch_a<R>(h, a, first | A_RK_THIS | A_FWD, 0, 0);
+        HIP_RET(launch_a<R>(h, a, first | A_RK_THIS | A_FWD, 0, 0));
         for (int j = 0; j < nz; ++j) {
-            launch_mixed<R>(h, a, 1, j == 0 ? (first | A_RK_THIS | A_FWD) : mid, j);      // rows of half 0
-            launch_mixed<R>(h, a, 0, j + 1 < nz ? mid : (A_INV | A_RK_PREV | last), j + 1);  // rows of half 1
+            HIP_RET(launch_mixed<R>(h, a, 1, j == 0 ? (first | A_RK_THIS | A_FWD) : mid, j));      // rows of half 0
+            HIP_RET(launch_mixed<R>(h, a, 0, j + 1 < nz ? mid : (A_INV | A_RK_PREV | last), j + 1));  // rows of half 1
         }
-        launch_a<R>(h, a, A_INV | A_RK_PREV | last, nz, 1);
-        return;
+        return launch_a<R>(h, a, A_INV | A_RK_PREV | last, nz, 1);
     }
-    launch_a<R>(h, a, first | A_RK_THIS | A_FWD, 0);
+    HIP_RET(launch_a<R>(h, a, first | A_RK_THIS | A_FWD, 0));
     for (int j = 0; j < nz; ++j) {
-        launch_b<R>(h, a, B_DISP, j);
-        if (j + 1 < nz) launch_a<R>(h, a, A_INV | A_RK_PREV | A_RK_THIS | A_FWD, j + 1);
-        else launch_a<R>(h, a, A_INV | A_RK_PREV | last, nz);
+        HIP_RET(launch_b<R>(h, a, B_DISP, j));
+        if (j + 1 < nz) HIP_RET(launch_a<R>(h, a, A_INV | A_RK_PREV | A_RK_THIS | A_FWD, j + 1));
+        else HIP_RET(launch_a<R>(h, a, A_INV | A_RK_PREV | last, nz));
     }
+    return hipSuccess;
 }
 
-// One cavity round trip (loop order of Sec. 4.1).
-template <typename R> static void enqueue_roundtrip(opo_t *h)
+// One cavity round trip (loop order of Sec. 4.1). Its refresh launch keeps
+// the state it starts from in d_snap.
+template <typename R> static hipError_t enqueue_roundtrip(opo_t *h)
 {
     StepArgs<R> a = base_args<R>(h, h->state);
     a.dz_arg = 0.0;
     a.zbase = 0.0;
+    a.snap = static_cast<cplx<R> *>(h->d_snap);
     const int eom = h->any_eom ? A_EOM : 0;
     const int K = h->n_stage;
     // the crystals in order, each from its own entrance; the boundary after the last
@@ -586,19 +608,20 @@ template <typename R> static void enqueue_roundtrip(opo_t *h)
         a.nz = h->stage_nz[st];
         const int first = st == 0 ? A_REFRESH : 0;
         if (st + 1 < K) {
-            enqueue_pass<R>(h, a, a.nz, first, 0);
+            HIP_RET(enqueue_pass<R>(h, a, a.nz, first, 0));
         } else if (h->any_gdd) {
-            enqueue_pass<R>(h, a, a.nz, first, A_ENERGY | A_FWD);
-            launch_b<R>(h, a, B_GDD);
-            launch_a<R>(h, a, A_INV | A_MIRROR | eom, 0);
+            HIP_RET(enqueue_pass<R>(h, a, a.nz, first, A_ENERGY | A_FWD));
+            HIP_RET(launch_b<R>(h, a, B_GDD));
+            HIP_RET(launch_a<R>(h, a, A_INV | A_MIRROR | eom, 0));
         } else {
-            enqueue_pass<R>(h, a, a.nz, first, A_ENERGY | A_MIRROR | eom);
+            HIP_RET(enqueue_pass<R>(h, a, a.nz, first, A_ENERGY | A_MIRROR | eom));
         }
     }
-    prof_begin(h, OPO_K_ENERGY);
+    HIP_RET(prof_begin(h, OPO_K_ENERGY));
     energy_reduce<<<1, kThreads, 0, h->stream>>>(h->d_inst, h->n_inst, h->d_partial, h->d_hist,
                                                  h->d_counter, kHistChunk);
-    prof_end(h);
+    HIP_RET(hipGetLastError());
+    return prof_end(h);
 }
 
 template <typename R> static int setup_kernels(opo_t *h)
@@ -906,7 +929,12 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         if (hipMalloc(&h->d_record, static_cast<size_t>(opt.record_rt) * need) != hipSuccess)
             return bail(fail(OPO_ENOMEM, "hipMalloc of the round-trip record failed"));
         h->record_cap = opt.record_rt;
+        // slots of round trips that never ran here (before a restored position) read as zeros
+        if (hipMemsetAsync(h->d_record, 0, static_cast<size_t>(opt.record_rt) * need, h->stream) != hipSuccess)
+            return bail(fail(OPO_EDEVICE, "clearing the round-trip record failed"));
     }
+    if (hipMalloc(&h->d_snap, need) != hipSuccess)
+        return bail(fail(OPO_ENOMEM, "hipMalloc of the round-trip snapshot failed"));
     if (hipMalloc(reinterpret_cast<void **>(&h->d_inst), h->inst.size() * sizeof(InstDesc)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_tile_a), h->tiles_a * sizeof(int)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_tile_b), h->tiles_b * sizeof(int)) != hipSuccess ||
@@ -916,7 +944,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         hipMalloc(reinterpret_cast<void **>(&h->d_partial), h->tiles_a * 3 * sizeof(double)) != hipSuccess ||
         hipMalloc(reinterpret_cast<void **>(&h->d_hist),
                   static_cast<size_t>(kHistChunk) * n * 3 * sizeof(double)) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void **>(&h->d_counter), 2 * sizeof(int)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&h->d_counter), 4 * sizeof(int)) != hipSuccess ||
         (h->mixed && (hipMalloc(reinterpret_cast<void **>(&h->d_map[0]), maps[0].size() * sizeof(int)) != hipSuccess ||
                       hipMalloc(reinterpret_cast<void **>(&h->d_map[1]), maps[1].size() * sizeof(int)) != hipSuccess)))
         return bail(fail(OPO_ENOMEM, "hipMalloc of the tables failed"));
@@ -947,8 +975,9 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         (h->mixed && hipMemcpyAsync(h->d_map[1], maps[1].data(), maps[1].size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess) ||
         hipStreamSynchronize(st) != hipSuccess)
         return bail(fail(OPO_EDEVICE, "upload of the instance tables failed"));
-    if (opt.precision == OPO_F64) upload_phasors<double>(h->d_tw, twre, twim, st);
-    else upload_phasors<float>(h->d_tw, twre, twim, st);
+    if ((opt.precision == OPO_F64 ? upload_phasors<double>(h->d_tw, twre, twim, st)
+                                  : upload_phasors<float>(h->d_tw, twre, twim, st)) != hipSuccess)
+        return bail(fail(OPO_EDEVICE, "upload of the FFT twiddles failed"));
     {
         // W_nt^{j1 k2} = e^{-2 pi i (j1 k2 mod nt)/nt} in FP64 at k2 * n1 + j1
         std::vector<double> wre(static_cast<size_t>(w4_elems)), wim(static_cast<size_t>(w4_elems));
@@ -962,8 +991,9 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
                     wim[e.second + k2 * n1 + j1] = -std::sin(a);
                 }
         }
-        if (opt.precision == OPO_F64) upload_phasors<double>(h->d_w4tab, wre, wim, st);
-        else upload_phasors<float>(h->d_w4tab, wre, wim, st);
+        if ((opt.precision == OPO_F64 ? upload_phasors<double>(h->d_w4tab, wre, wim, st)
+                                      : upload_phasors<float>(h->d_w4tab, wre, wim, st)) != hipSuccess)
+            return bail(fail(OPO_EDEVICE, "upload of the four-step twiddles failed"));
     }
     std::vector<double> zeros;
     for (int i = 0; i < n; ++i) {
@@ -975,16 +1005,18 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
             src = zeros.data();
         }
         char *dst = static_cast<char *>(h->state) + d.off * es;
-        if (opt.precision == OPO_F64) host_to_state<double>(dst, src, count, st);
-        else host_to_state<float>(dst, src, count, st);
+        if ((opt.precision == OPO_F64 ? host_to_state<double>(dst, src, count, st)
+                                      : host_to_state<float>(dst, src, count, st)) != hipSuccess)
+            return bail(fail(OPO_EDEVICE, "upload of the initial fields failed"));
         if (f[i].pump_in) {
             char *pd = static_cast<char *>(h->pump) + d.pump_off * es;
             const long long count = static_cast<long long>(d.nt) * d.pump_windows;
-            if (opt.precision == OPO_F64) host_to_state<double>(pd, f[i].pump_in, count, st);
-            else host_to_state<float>(pd, f[i].pump_in, count, st);
+            if ((opt.precision == OPO_F64 ? host_to_state<double>(pd, f[i].pump_in, count, st)
+                                          : host_to_state<float>(pd, f[i].pump_in, count, st)) != hipSuccess)
+                return bail(fail(OPO_EDEVICE, "upload of the input pump failed"));
         }
     }
-    set_counter<<<1, 1, 0, st>>>(h->d_counter, 0, 0);
+    set_counter<<<1, 1, 0, st>>>(h->d_counter, 0, 0, 1);
     int krc = opt.precision == OPO_F64 ? setup_kernels<double>(h) : setup_kernels<float>(h);
     if (krc) return bail(krc);
     hipError_t le = hipGetLastError();
@@ -1048,8 +1080,7 @@ template <typename R> static int propagate_impl(opo_t *h, int nz, double dz)
     StepArgs<R> a = base_args<R>(h, h->state);
     a.dz_arg = dz;
     a.zbase = h->z;
-    enqueue_pass<R>(h, a, nz, 0, 0);
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(enqueue_pass<R>(h, a, nz, 0, 0));
     h->z += nz * dz;
     const size_t used = h->ev_used;
     h->ev_used = 0;
@@ -1065,7 +1096,7 @@ template <typename R> static int propagate_impl(opo_t *h, int nz, double dz)
 // sums and the control decision. Every launch argument is fixed once the
 // buffers exist (z, dz, tol and the budget live in the control state), so
 // the sequence is captured once into a graph and replayed.
-template <typename R> static void enqueue_attempt(opo_t *h)
+template <typename R> static hipError_t enqueue_attempt(opo_t *h)
 {
     const int blocks = h->a_chunks * h->n_inst;
     cplx<R> *u = static_cast<cplx<R> *>(h->state), *uc = static_cast<cplx<R> *>(h->a_uc),
@@ -1075,25 +1106,28 @@ template <typename R> static void enqueue_attempt(opo_t *h)
     a.adapt = h->d_actl;
     a.disp = tab;
     adapt_begin<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, h->d_actl, h->a_chunks, u, uc, uf, tab);
+    HIP_RET(hipGetLastError());
     a.state = uc;                 // one step of dz, from u
     a.adapt_scale = 1.0;
     a.src = u;
-    launch_a<R>(h, a, A_RK_THIS | A_FWD, 0);
+    HIP_RET(launch_a<R>(h, a, A_RK_THIS | A_FWD, 0));
     a.src = nullptr;
-    launch_b<R>(h, a, B_DISP, 0, 0);
-    launch_a<R>(h, a, A_INV | A_RK_PREV, 1);
+    HIP_RET(launch_b<R>(h, a, B_DISP, 0, 0));
+    HIP_RET(launch_a<R>(h, a, A_INV | A_RK_PREV, 1));
     a.state = uf;                 // two steps of dz/2, from u
     a.adapt_scale = 0.5;
     a.src = u;
-    launch_a<R>(h, a, A_RK_THIS | A_FWD, 0);
+    HIP_RET(launch_a<R>(h, a, A_RK_THIS | A_FWD, 0));
     a.src = nullptr;
-    launch_b<R>(h, a, B_DISP, 0, 0);
-    launch_a<R>(h, a, A_INV | A_RK_PREV | A_RK_THIS | A_FWD, 1);
-    launch_b<R>(h, a, B_DISP, 1, 0);
-    launch_a<R>(h, a, A_INV | A_RK_PREV, 2);
+    HIP_RET(launch_b<R>(h, a, B_DISP, 0, 0));
+    HIP_RET(launch_a<R>(h, a, A_INV | A_RK_PREV | A_RK_THIS | A_FWD, 1));
+    HIP_RET(launch_b<R>(h, a, B_DISP, 1, 0));
+    HIP_RET(launch_a<R>(h, a, A_INV | A_RK_PREV, 2));
     adapt_error<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, h->d_actl, h->a_chunks, uc, uf, h->d_apart);
-    adapt_control<<<(h->n_inst + kThreads / 64 - 1) / (kThreads / 64), kThreads, 0, h->stream>>>(h->d_actl, h->n_inst, h->a_chunks, h->d_apart, 1, 0.0, 0.0, 0.0,
-                                                 0.0, 0);
+    HIP_RET(hipGetLastError());
+    adapt_control<<<(h->n_inst + kThreads / 64 - 1) / (kThreads / 64), kThreads, 0, h->stream>>>(
+        h->d_actl, h->n_inst, h->a_chunks, h->d_apart, 1, 0.0, 0.0, 0.0, 0.0, 0);
+    return hipGetLastError();
 }
 
 // Adaptive step: every instance from the handle's z over `length` (see
@@ -1131,8 +1165,12 @@ static int adaptive_impl(opo_t *h, double length, double tol, double dz0, int ma
     if (h->use_graph && !h->a_graph) {
         hipGraph_t g;
         HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        enqueue_attempt<R>(h);
+        const hipError_t qe = enqueue_attempt<R>(h);
         hipError_t ce = hipStreamEndCapture(h->stream, &g);
+        if (qe != hipSuccess) {
+            if (ce == hipSuccess) (void)hipGraphDestroy(g);
+            return fail(OPO_EDEVICE, std::string("adaptive attempt: ") + hipGetErrorString(qe));
+        }
         if (ce != hipSuccess) return fail(OPO_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
         ce = hipGraphInstantiate(&h->a_graph, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
@@ -1141,8 +1179,9 @@ static int adaptive_impl(opo_t *h, double length, double tol, double dz0, int ma
             return fail(OPO_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ce));
         }
     }
-    adapt_control<<<(h->n_inst + kThreads / 64 - 1) / (kThreads / 64), kThreads, 0, h->stream>>>(h->d_actl, h->n_inst, h->a_chunks, h->d_apart, 0, h->z, length,
-                                                 dz0, tol, max_attempts);
+    adapt_control<<<(h->n_inst + kThreads / 64 - 1) / (kThreads / 64), kThreads, 0, h->stream>>>(
+        h->d_actl, h->n_inst, h->a_chunks, h->d_apart, 0, h->z, length, dz0, tol, max_attempts);
+    HIP_TRY(hipGetLastError());
     std::vector<AdaptState> ctl(h->n_inst);
     HIP_TRY(hipMemcpyAsync(ctl.data(), h->d_actl, ctl.size() * sizeof(AdaptState), hipMemcpyDeviceToHost,
                            h->stream));
@@ -1165,7 +1204,7 @@ static int adaptive_impl(opo_t *h, double length, double tol, double dz0, int ma
             if (h->a_graph) {
                 HIP_TRY(hipGraphLaunch(h->a_graph, h->stream));
             } else {
-                enqueue_attempt<R>(h);
+                HIP_TRY(enqueue_attempt<R>(h));
             }
         }
         HIP_TRY(hipGetLastError());
@@ -1196,6 +1235,12 @@ static int adaptive_impl(opo_t *h, double length, double tol, double dz0, int ma
     return OPO_OK;
 }
 
+// Round trips in chunks of up to kHistChunk graph replays, the energy rows of
+// each chunk read back at its end. A round trip with non-finite energies (or
+// a non-finite value stored at its end) sets the device stop flag: every later
+// launch of the call stores nothing, the round trip's row is not counted, and
+// the state is restored from the snapshot its refresh launch took, i.e. to the
+// end of the last finite round trip.
 template <typename R> static int roundtrip_impl(opo_t *h, int n_rt)
 {
     int trc = ensure_tables<R>(h, 0.0);
@@ -1203,8 +1248,12 @@ template <typename R> static int roundtrip_impl(opo_t *h, int n_rt)
     if (h->use_graph && !h->graph) {
         hipGraph_t g;
         HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        enqueue_roundtrip<R>(h);
+        const hipError_t qe = enqueue_roundtrip<R>(h);
         hipError_t ce = hipStreamEndCapture(h->stream, &g);
+        if (qe != hipSuccess) {
+            if (ce == hipSuccess) (void)hipGraphDestroy(g);
+            return fail(OPO_EDEVICE, std::string("round trip: ") + hipGetErrorString(qe));
+        }
         if (ce != hipSuccess) return fail(OPO_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
         ce = hipGraphInstantiate(&h->graph, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
@@ -1213,38 +1262,46 @@ template <typename R> static int roundtrip_impl(opo_t *h, int n_rt)
             return fail(OPO_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ce));
         }
     }
-    int bad = -1;
     int done = 0;
     std::vector<double> chunk;
+    int ctr[4] = {0, 0, 0, 0};
     while (done < n_rt) {
         const int m = std::min(kHistChunk, n_rt - done);
-        set_counter<<<1, 1, 0, h->stream>>>(h->d_counter, 0, -1);
+        set_counter<<<1, 1, 0, h->stream>>>(h->d_counter, 0, -1, 0);
+        HIP_TRY(hipGetLastError());
         for (int r = 0; r < m; ++r) {
             if (h->graph) {
                 HIP_TRY(hipGraphLaunch(h->graph, h->stream));
             } else {
-                enqueue_roundtrip<R>(h);
+                HIP_TRY(enqueue_roundtrip<R>(h));
                 const size_t used = h->ev_used;
                 h->ev_used = 0;
                 int prc = prof_collect(h, used);
                 if (prc) return prc;
             }
         }
-        HIP_TRY(hipGetLastError());
         chunk.resize(static_cast<size_t>(m) * h->n_inst * 3);
         HIP_TRY(hipMemcpyAsync(chunk.data(), h->d_hist, chunk.size() * sizeof(double),
                                hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipMemcpyAsync(ctr, h->d_counter, sizeof(ctr), hipMemcpyDeviceToHost, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
-        for (size_t q = 0; q < chunk.size(); ++q)
-            if (bad < 0 && !std::isfinite(chunk[q]))
-                bad = h->hist_rows + static_cast<int>(q / (3 * h->n_inst));
-        h->hist.insert(h->hist.end(), chunk.begin(), chunk.end());
-        h->hist_rows += m;
+        const int rows = std::min(ctr[0], m);   // finite round trips of this chunk
+        h->hist.insert(h->hist.end(), chunk.begin(), chunk.begin() + static_cast<size_t>(rows) * h->n_inst * 3);
+        h->hist_rows += rows;
+        if (ctr[2] != 0) {
+            // back to the end of the last finite round trip, flags cleared
+            HIP_TRY(hipMemcpyAsync(h->state, h->d_snap, h->state_bytes, hipMemcpyDeviceToDevice, h->stream));
+            set_counter<<<1, 1, 0, h->stream>>>(h->d_counter, 0, -1, 1);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            h->z = 0.0;
+            return fail(OPO_ENONFINITE, "non-finite energy or field at round trip " + std::to_string(h->hist_rows) +
+                                            " (counted from opo_init); stopped with the state that round trip "
+                                            "started from");
+        }
         done += m;
     }
     h->z = 0.0;
-    if (bad >= 0)
-        return fail(OPO_ENONFINITE, "non-finite energy at round trip " + std::to_string(bad));
     return OPO_OK;
 }
 
@@ -1257,9 +1314,8 @@ template <typename R> static int spectrum_impl(opo_t *h, int inst, int field, do
     }
     HIP_TRY(hipMemcpyAsync(h->scratch, h->state, h->state_bytes, hipMemcpyDeviceToDevice, h->stream));
     StepArgs<R> a = base_args<R>(h, h->scratch);
-    launch_a<R>(h, a, A_FWD, 0);
-    launch_b<R>(h, a, B_FWD_ONLY);
-    HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_a<R>(h, a, A_FWD, 0));
+    HIP_TRY(launch_b<R>(h, a, B_FWD_ONLY));
     std::vector<double> tmp(2 * static_cast<size_t>(d.nt));
     const char *src = static_cast<const char *>(h->scratch) + (d.off + static_cast<long long>(field) * d.nt) * h->elem;
     HIP_TRY(state_to_host<R>(tmp.data(), src, d.nt, h->stream));
@@ -1393,10 +1449,41 @@ int opo_set_fields(opo_t *h, int32_t inst, int32_t field, const double *in)
         const InstDesc &d = h->inst[inst];
         char *dst = static_cast<char *>(h->state) + (d.off + static_cast<long long>(field) * d.nt) * h->elem;
         HIP_TRY(hipStreamSynchronize(h->stream));
-        if (h->precision == OPO_F64) host_to_state<double>(dst, in, d.nt, h->stream);
-        else host_to_state<float>(dst, in, d.nt, h->stream);
-        HIP_TRY(hipGetLastError());
+        HIP_TRY(h->precision == OPO_F64 ? host_to_state<double>(dst, in, d.nt, h->stream)
+                                        : host_to_state<float>(dst, in, d.nt, h->stream));
         h->z = 0.0;
+        return OPO_OK;
+    } catch (...) {
+        return fail(OPO_ENOMEM, "host allocation failed");
+    }
+}
+
+int opo_get_progress(opo_t *h, int32_t *rt_done, double *z_mm)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    if (rt_done) *rt_done = h->hist_rows;
+    if (z_mm) *z_mm = h->z;
+    return OPO_OK;
+}
+
+int opo_set_progress(opo_t *h, int32_t rt_done, double z_mm, const double *history)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    if (rt_done < 0 || (rt_done > 0 && !history) || !(z_mm >= 0.0) || !std::isfinite(z_mm))
+        return fail(OPO_EINVAL, "need rt_done >= 0, a history for rt_done > 0, and finite z_mm >= 0");
+    try {
+        std::vector<double> hist(history, history + static_cast<size_t>(rt_done) * h->n_inst * 3);
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        // the device count of completed round trips selects the input-pump window
+        // and the record slot of the next one
+        set_counter<<<1, 1, 0, h->stream>>>(h->d_counter, 0, rt_done, 1);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        h->hist.swap(hist);
+        h->hist_rows = rt_done;
+        h->z = z_mm;
         return OPO_OK;
     } catch (...) {
         return fail(OPO_ENOMEM, "host allocation failed");

@@ -107,7 +107,12 @@ template <typename R> struct StepArgs {
     const Phasor<R> *w4tab;   // four-step twiddles W_nt^{j1 k2} per (nt, n1), from FP64
     const Phasor<R> *disp;    // linear-propagator tables H_x(k)/nt in row-pass order
     double *partial;          // [column tiles][3] energy partial sums
-    const int *counter;       // [0] energy-history slot, [1] round trips completed
+    // [0] energy-history slot, [1] round trips completed, [2] stop: a round
+    // trip had non-finite energies (every later tile of the call stores
+    // nothing), [3] a boundary launch stored a non-finite value
+    int *counter;
+    cplx<R> *snap;            // round trips: A_REFRESH tiles first copy the fields
+                              // they load here (the state the round trip starts from)
     cplx<R> *record;          // per-round-trip record of the fields leaving the crystal, or null
     long long record_stride;  // elements per record slot (the whole state)
     int record_cap;           // record slots
@@ -485,6 +490,9 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     const int nt = d.nt, n1 = d.n1;
     const int j1 = (tile - d.tile_a0) * COLS + c;
     const bool act = j1 < n1;
+    // a round trip of this call had non-finite energies: compute, store nothing
+    // (the flag is first needed at the stores, so its load hides behind the field loads)
+    const bool stopped = a.counter[2] != 0;
     V *g = a.state + d.off + j1;
     const V *gs = (a.src ? a.src : a.state) + d.off + j1;
 
@@ -513,6 +521,16 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
         for (int m = 0; m < PF; ++m)
             v[f][m] = act ? gs[static_cast<long long>(f) * nt + static_cast<long long>(n1) * (t + m * T)]
                           : mk<V>(R(0), R(0));
+    // the state this round trip starts from (time samples: A_REFRESH never
+    // follows an inverse transform), kept to restore after a non-finite one
+    if ((flags & A_REFRESH) && a.snap != nullptr && act && !stopped) {
+        V *sp = a.snap + d.off + j1;
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int m = 0; m < PF; ++m)
+                sp[static_cast<long long>(f) * nt + static_cast<long long>(n1) * (t + m * T)] = v[f][m];
+    }
 
     int base[NF];
 #pragma unroll
@@ -538,7 +556,8 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     // round trips completed: the window of a long input pump that the refresh
     // reads, and the record slot of the pass that A_ENERGY ends
     const int rt = (flags & (A_REFRESH | A_ENERGY)) ? a.counter[1] : 0;
-    const bool rec = (flags & A_ENERGY) && a.record != nullptr && rt < a.record_cap && act;
+    const bool rec = (flags & A_ENERGY) && a.record != nullptr && rt < a.record_cap && act && !stopped;
+    bool nonfinite = false;              // a boundary value about to be stored is NaN or Inf
     V *rg = rec ? a.record + static_cast<long long>(rt) * a.record_stride + d.off + j1 : nullptr;
     long long pwin = 0;                  // offset of the input-pump window, -1 = past the last
     if (d.pump_windows > 1) pwin = rt < d.pump_windows ? static_cast<long long>(rt) * nt : -1;
@@ -582,16 +601,22 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
             if (NF == 3 && !(d.res_mask & 4)) y2 = mk<V>(R(0), R(0));
         }
         if (flags & A_RK_THIS) rk4_fields<R, NF>(*cpl, 1, imag, kerr, y0, y1, y2);
+        if (flags & A_MIRROR)
+            nonfinite = nonfinite || !(isfinite(y0.x) && isfinite(y0.y) && isfinite(y1.x) && isfinite(y1.y) &&
+                                       isfinite(y2.x) && isfinite(y2.y));
         v[0][m] = y0;
         v[1][m] = y1;
         if constexpr (NF == 3) v[2][m] = y2;
     }
     if (flags & A_ENERGY) {
         block_sum3(en, red);
-        if (threadIdx.x == 0)
+        if (threadIdx.x == 0 && !stopped)
             for (int x = 0; x < 3; ++x)
                 a.partial[tile * 3 + x] = en[x];
     }
+    // the end of a round trip: energy_reduce treats a non-finite stored field like
+    // a non-finite energy (benign race: every writer stores 1)
+    if (nonfinite && act && !stopped) a.counter[3] = 1;
 
     if (flags & A_FWD) {
         column_fft<R, LN2, PF, NF, -1, COLS>(v, s, base, t, a.tw);
@@ -604,7 +629,7 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
             }
         }
     }
-    if (act) {
+    if (act && !stopped) {
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
@@ -653,6 +678,7 @@ __device__ __forceinline__ void row_tile(const StepArgs<R> &a, const InstDesc &d
     const int f = local / blocks;
     const int k2 = (local - f * blocks) * ROWS + w;
     const bool act = k2 < n2;
+    const bool stopped = a.counter[2] != 0;   // see column_tile
     V *g = a.state + d.off + static_cast<long long>(f) * nt + static_cast<long long>(N) * k2 + t;
 
     V v[1][PF];
@@ -695,7 +721,7 @@ __device__ __forceinline__ void row_tile(const StepArgs<R> &a, const InstDesc &d
         }
         reg_fft<R, N, PF, 1, +1, 1>(v, s, base, t, a.tw);
     }
-    if (act)
+    if (act && !stopped)
 #pragma unroll
         for (int m = 0; m < PF; ++m)
             g[m * T] = v[0][m];
@@ -863,99 +889,21 @@ __global__ __launch_bounds__(kThreads) void adapt_error(const InstDesc *inst, co
 // spent, else cut a step that would pass the end.
 __global__ __launch_bounds__(kThreads) void adapt_control(AdaptState *ctl, int n_inst, int chunks,
                                                           const double *part, int mode, double z0, double length,
-                                                          double dz0, double tol, int max_attempts)
-{
-    const int lane = threadIdx.x & 63;
-    for (int ii = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6); ii < n_inst; ii += gridDim.x * (kThreads / 64)) {
-        // error sums of the attempt: lane-strided partials, then a fixed shuffle tree
-        double num = 0.0, den = 0.0;
-        if (mode == 1)
-            for (int c = lane; c < chunks; c += 64) {
-                num += part[2 * (static_cast<long long>(ii) * chunks + c)];
-                den += part[2 * (static_cast<long long>(ii) * chunks + c) + 1];
-            }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            num += __shfl_down(num, o, 64);
-            den += __shfl_down(den, o, 64);
-        }
-        if (lane != 0) continue;
-        AdaptState st = ctl[ii];
-        if (mode == 0) {
-            st.z = z0;
-            st.end = z0 + length;
-            st.dz = dz0;
-            st.tol = tol;
-            st.max_attempts = max_attempts;
-            st.status = 0;
-            st.last = 0;
-            st.pend = 0;
-            st.accepted = 0;
-            st.rejected = 0;
-        } else if (st.status == 0) {
-            const double dd = sqrt(num / den);
-            const double tol = st.tol;
-            if (dd > 2.0 * tol) {
-                st.dz *= 0.5;
-                st.rejected += 1;
-                st.pend = 0;
-            } else {
-                st.z = st.last ? st.end : st.z + st.dz;
-                st.accepted += 1;
-                st.pend = 1;
-                if (dd > tol) st.dz /= kAdaptGrow;
-                else if (dd < 0.5 * tol) st.dz *= kAdaptGrow;
-            }
-        } else {
-            st.pend = 0;      // extrapolated by the begin of this attempt
-        }
-        if (st.status == 0) {
-            if (!(st.z < st.end)) {
-                st.status = 1;
-            } else if (st.accepted + st.rejected >= st.max_attempts) {
-                st.status = 2;
-            } else {
-                const double rest = st.end - st.z;
-                st.last = rest <= st.dz * kAdaptSlack;
-                if (st.last) st.dz = rest;
-            }
-        }
-        ctl[ii] = st;
-    }
-}
+                                                          double dz0, double tol, int max_attempts);
 
 // ------------------------------------------------------------------------
 // Per-instance energies of one round trip from the column-tile partial sums,
-// summed in tile order (deterministic), into history row `*counter`.
+// summed in tile order (deterministic), into history row counter[0]. A
+// non-finite energy, or a non-finite value stored by the boundary launch
+// (counter[3]), sets the stop flag counter[2] instead: the row is not written,
+// the counters do not advance, and every later launch of the call stores
+// nothing, so the state the round trip started from (kept by its refresh
+// launch) is the last finite one.
 __global__ __launch_bounds__(kThreads) void energy_reduce(const InstDesc *inst, int n_inst,
                                                           const double *partial, double *hist,
-                                                          int *counter, int capacity)
-{
-    const int slot = *counter;
-    for (int ii = threadIdx.x; ii < n_inst; ii += kThreads) {
-        const InstDesc &d = inst[ii];
-        double e[3] = {0.0, 0.0, 0.0};
-        for (int t = 0; t < d.tiles_a; ++t)
-            for (int x = 0; x < 3; ++x)
-                e[x] += partial[(d.tile_a0 + t) * 3 + x];
-        if (slot < capacity)
-            for (int x = 0; x < 3; ++x)
-                hist[(static_cast<long long>(slot) * n_inst + ii) * 3 + x] = e[x];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        counter[0] = slot + 1;
-        counter[1] += 1;      // round trips completed
-    }
-}
+                                                          int *counter, int capacity);
 
-// counter[0] = slot; counter[1] = rt unless rt < 0.
-__global__ void set_counter(int *counter, int slot, int rt)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        counter[0] = slot;
-        if (rt >= 0) counter[1] = rt;
-    }
-}
+// counter[0] = slot; counter[1] = rt unless rt < 0; clear_flags: counter[2] = counter[3] = 0.
+__global__ void set_counter(int *counter, int slot, int rt, int clear_flags);
 
 } // namespace opo

@@ -10,7 +10,8 @@ import os
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libopo.so")
+# OPO_LIB selects another build of the library (the host-sanitizer build of the CPU tests)
+LIB_PATH = os.environ.get("OPO_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libopo.so")
 
 OPO_OK, OPO_EINVAL, OPO_ENOMEM, OPO_EDEVICE, OPO_ENONFINITE, OPO_ESTATE, OPO_ESTEPS = 0, -1, -2, -3, -4, -5, -6
 OPO_F32, OPO_F64 = 0, 1
@@ -19,7 +20,8 @@ STATUS = {0: "OPO_OK", -1: "OPO_EINVAL", -2: "OPO_ENOMEM", -3: "OPO_EDEVICE",
 
 EXPORTS = ("opo_state_bytes", "opo_init", "opo_init_batch", "ssfm_propagate", "ssfm_propagate_adaptive",
            "cavity_roundtrip",
-           "opo_sync", "opo_get_fields", "opo_set_fields", "opo_get_energy_history",
+           "opo_sync", "opo_get_fields", "opo_set_fields", "opo_get_progress", "opo_set_progress",
+           "opo_get_energy_history",
            "opo_get_power_history",
            "opo_get_record", "opo_get_grid", "opo_kernel_times", "opo_info", "opo_destroy",
            "opo_last_error")
@@ -90,6 +92,8 @@ def load():
     lib.opo_sync.argtypes = [P]
     lib.opo_get_fields.argtypes = [P, I, I, I, P]
     lib.opo_set_fields.argtypes = [P, I, I, P]
+    lib.opo_get_progress.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(D)]
+    lib.opo_set_progress.argtypes = [P, I, D, P]
     lib.opo_get_energy_history.argtypes = [P, I, P, I, ctypes.POINTER(I)]
     lib.opo_get_record.argtypes = [P, I, I, I, P]
     lib.opo_get_power_history.argtypes = [P, I, D, P, I, ctypes.POINTER(I)]
@@ -101,7 +105,8 @@ def load():
     lib.opo_last_error.restype = ctypes.c_char_p
     for name in ("opo_init", "opo_init_batch", "ssfm_propagate", "ssfm_propagate_adaptive",
                  "cavity_roundtrip", "opo_sync",
-                 "opo_get_fields", "opo_set_fields", "opo_get_energy_history", "opo_get_record",
+                 "opo_get_fields", "opo_set_fields", "opo_get_progress", "opo_set_progress",
+                 "opo_get_energy_history", "opo_get_record",
                  "opo_get_power_history",
                  "opo_get_grid",
                  "opo_kernel_times", "opo_info", "opo_destroy"):
@@ -265,6 +270,32 @@ class Opo:
         for x in range(nf):
             row = np.ascontiguousarray(a[x])
             _check(self._lib.opo_set_fields(self.h, inst, x, row.ctypes.data))
+
+    def progress(self):
+        """(round trips completed since opo_init, z of the next ssfm_propagate)."""
+        rt, z = ctypes.c_int32(), ctypes.c_double()
+        _check(self._lib.opo_get_progress(self.h, ctypes.byref(rt), ctypes.byref(z)))
+        return rt.value, z.value
+
+    def set_progress(self, rt_done, z, history):
+        """Continue as after rt_done round trips, z (see include/opo.h); history has shape
+        (rt_done, instances, 3)."""
+        hist = np.ascontiguousarray(np.asarray(history, dtype=np.float64).reshape(int(rt_done), self.n, 3))
+        _check(self._lib.opo_set_progress(self.h, int(rt_done), float(z),
+                                          hist.ctypes.data if rt_done else None))
+
+    def checkpoint(self):
+        """Everything a handle built from the same inputs needs to resume this run bit for
+        bit: fields of every instance, the energy histories, round trips completed, z."""
+        rt, z = self.progress()
+        hist = np.stack([self.energy_history(i) for i in range(self.n)], axis=1) if rt else \
+            np.zeros((0, self.n, 3))
+        return {"fields": [self.get_fields(i) for i in range(self.n)], "history": hist, "rt_done": rt, "z": z}
+
+    def restore(self, ck):
+        for i, a in enumerate(ck["fields"]):
+            self.set_fields(a, i)
+        self.set_progress(ck["rt_done"], ck["z"], ck["history"])
 
     def energy_history(self, inst=0):
         rows = ctypes.c_int32()

@@ -116,6 +116,20 @@ def test_calls_on_invalid_handles():
     out = np.zeros(8)
     assert lib.opo_get_fields(None, 0, 0, 0, out.ctypes.data) == B.OPO_ESTATE
     assert "handle" in B.last_error()
+    rt, z = ctypes.c_int32(), ctypes.c_double()
+    assert lib.opo_get_progress(bogus, ctypes.byref(rt), ctypes.byref(z)) == B.OPO_ESTATE
+    assert lib.opo_set_progress(None, 0, 0.0, None) == B.OPO_ESTATE
+
+
+def test_bad_device_ordinal_is_reported():
+    """A device ordinal no HIP device has (the library checks the device before it
+    allocates anything)."""
+    n, f, c, k, keep = _one()
+    lib = B.load()
+    h = ctypes.c_void_p()
+    opt = B.OptionsT(device=97)
+    assert lib.opo_init_batch(ctypes.byref(h), 1, f, c, k, ctypes.byref(opt)) == B.OPO_EDEVICE
+    assert h.value is None and "ordinal 97" in B.last_error()
 
 
 def test_no_device_is_reported():

@@ -1,0 +1,239 @@
+"""Non-finite round trips and bitwise resume, through the C ABI on the GPU.
+
+cavity_roundtrip stops at the first round trip whose energies (or final fields)
+are not finite, appends no row for it, and leaves the fields, z and the count
+of round trips completed as after the last finite round trip (the too-large
+step of Sec. 2.4 ends in NaN). A run saved after some round trips and restored
+into a fresh handle continues bit for bit (the per-round-trip save of Sec. 4.1).
+Every comparison here is between runs of the same kernels on the same data, so
+it is exact.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import torch  # noqa: F401
+
+import oracle
+from paper_2410_02532_amd import opo as B
+from paper_2410_02532_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _same(a, b):
+    return np.array_equal(a, b, equal_nan=True)
+
+
+def _runaway(nt=256, nz=5, gdd=0.0):
+    """A CW SRO whose crystal amplifies every field (negative loss): the FP32 fields
+    overflow after some tens of round trips, deterministically."""
+    w = W.config("sro_cw", nt=nt, nz=nz)
+    w["crystal"] = dict(w["crystal"], alpha_per_mm=(-2.0, -2.0, -2.0))
+    if gdd:
+        w["cavity"] = W.cavity(gdd_fs2=gdd)
+    return w
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_injected_nan_stops_with_the_last_finite_state(graph):
+    """k finite round trips, then a NaN set into the signal: the next call stops in its
+    first round trip, keeps the k rows, and leaves the fields as set (the state that round
+    trip started from); finite fields set back continue exactly like an uninterrupted run."""
+    say("injected NaN, graph=%s" % graph)
+    w = W.config("sro_cw", nt=512, nz=6)
+    k = 3
+    with B.from_workload(w, use_graph=graph) as ref:
+        ref.cavity_roundtrip(k + 2)
+        f_ref, e_ref = ref.get_fields(), ref.energy_history()
+    with B.from_workload(w, use_graph=graph) as h:
+        h.cavity_roundtrip(k)
+        good = h.get_fields()
+        rows = h.energy_history()
+        bad = good.copy()
+        bad[1, 17] = np.nan
+        h.set_fields(bad)
+        with pytest.raises(B.OpoError) as ei:
+            h.cavity_roundtrip(6)
+        assert ei.value.code == B.OPO_ENONFINITE
+        assert "round trip %d" % k in str(ei.value)
+        assert h.progress() == (k, 0.0)
+        assert _same(h.energy_history(), rows)
+        assert _same(h.get_fields(), bad)
+        # a repeated call stops at the same place with the same state
+        with pytest.raises(B.OpoError):
+            h.cavity_roundtrip(1)
+        assert h.progress() == (k, 0.0) and _same(h.get_fields(), bad)
+        h.set_fields(good)
+        h.cavity_roundtrip(2)
+        assert _same(h.get_fields(), f_ref)
+        assert _same(h.energy_history(), e_ref)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+@pytest.mark.parametrize("gdd", [0.0, 500.0])
+def test_overflow_stops_at_the_last_finite_round_trip(graph, gdd):
+    """A run that overflows inside a call: it returns OPO_ENONFINITE with m rows, where m
+    is the first round trip whose energies or final fields are not finite, and every field
+    equals, bit for bit, that of a fresh run of exactly m round trips (with a GDD element,
+    whose row pass and closing column launch also obey the stop)."""
+    say("overflow stop, graph=%s gdd=%g" % (graph, gdd))
+    w = _runaway(gdd=gdd)
+    with B.from_workload(w, use_graph=graph) as h:
+        with pytest.raises(B.OpoError) as ei:
+            h.cavity_roundtrip(400)
+        assert ei.value.code == B.OPO_ENONFINITE
+        m, z = h.progress()
+        assert 5 < m < 400 and z == 0.0
+        f, e = h.get_fields(), h.energy_history()
+    assert e.shape == (m, 3) and np.all(np.isfinite(e))
+    assert np.all(np.isfinite(f))
+    with B.from_workload(w, use_graph=graph) as g:
+        g.cavity_roundtrip(m)
+        assert _same(g.get_fields(), f)
+        assert _same(g.energy_history(), e)
+        with pytest.raises(B.OpoError):
+            g.cavity_roundtrip(1)          # round trip m itself is the non-finite one
+        assert g.progress() == (m, 0.0) and _same(g.get_fields(), f)
+
+
+def test_overflow_in_a_mixed_batch():
+    """In a batch run by the mixed launches (sizes 2^12 and 2^13 share one column and one
+    row kernel, so the two halves run in mixed launches), the first instance to overflow
+    stops the whole call; every instance is left after the last finite round trip of the
+    batch."""
+    say("overflow stop, mixed batch")
+    insts = []
+    for b, nt in enumerate([4096, 8192, 4096, 8192]):
+        w = _runaway(nt=nt) if b == 2 else W.config("sro_cw", nt=nt, nz=5, seed=50 + b)
+        insts.append(dict(w, nz=5))
+    with B.Opo(insts, 5) as h:
+        with pytest.raises(B.OpoError) as ei:
+            h.cavity_roundtrip(400)
+        assert ei.value.code == B.OPO_ENONFINITE
+        m = h.progress()[0]
+        got = [(h.get_fields(i), h.energy_history(i)) for i in range(4)]
+    with B.Opo(insts, 5) as g:
+        g.cavity_roundtrip(m)
+        for i in range(4):
+            assert _same(g.get_fields(i), got[i][0]), i
+            assert _same(g.energy_history(i), got[i][1]), i
+    assert all(np.all(np.isfinite(x[0])) for x in got)
+
+
+def _resume_check(w, n1, n2, **kw):
+    """n1 + n2 round trips in one handle equal n1, a checkpoint, a fresh handle restored
+    from it and n2 more, bit for bit (fields, histories, position)."""
+    with B.from_workload(w, **kw) as a:
+        a.cavity_roundtrip(n1 + n2)
+        full = a.checkpoint()
+        rec_a = [a.record(r) for r in range(n1 + n2)] if kw.get("record_rt") else None
+    with B.from_workload(w, **kw) as b:
+        b.cavity_roundtrip(n1)
+        ck = b.checkpoint()
+    with B.from_workload(w, **kw) as c:
+        c.restore(ck)
+        assert c.progress() == (n1, 0.0)
+        c.cavity_roundtrip(n2)
+        got = c.checkpoint()
+        rec_c = [c.record(r) for r in range(n1 + n2)] if kw.get("record_rt") else None
+    assert (got["rt_done"], got["z"]) == (full["rt_done"], full["z"])
+    assert _same(got["history"], full["history"])
+    for x, y in zip(got["fields"], full["fields"]):
+        assert _same(x, y)
+    return rec_a, rec_c
+
+
+def test_resume_cw_sro():
+    say("resume, CW SRO")
+    _resume_check(W.config("sro_cw", nt=2048, nz=10), 5, 5)
+
+
+def test_resume_mixed_batch_f64():
+    say("resume, mixed batch f64")
+    insts = [dict(W.config("sro_cw", nt=nt, nz=8, seed=70 + b), nz=8) for b, nt in enumerate([4096, 8192, 4096, 8192])]
+    _resume_check(dict(instances=insts, nz=8), 4, 3, precision="f64")
+
+
+def test_resume_pulse_windows_and_record():
+    """The nanosecond regime: round trip m reads window m of the long pump and fills
+    record slot m, so the restored count must select windows 5.. and slots 5..; slots of
+    round trips before the restore read as zeros."""
+    say("resume, pump windows and record")
+    w = W.config("ns_pulsed")
+    # twelve windows from the middle of the 10 ns pulse
+    insts = [dict(ins, pump_in=ins["pump_in"][194:206]) for ins in w["instances"][:2]]
+    wl = dict(instances=insts, nz=w["nz"])
+    rec_a, rec_c = _resume_check(wl, 5, 5, record_rt=10)
+    for r in range(10):
+        if r < 5:
+            assert not np.any(rec_c[r])
+        else:
+            assert _same(rec_c[r], rec_a[r]), r
+
+
+def test_resume_continues_z_of_a_pass():
+    """ssfm_propagate continues z across a checkpoint (the mismatch phase depends on it)."""
+    say("resume, z of a pass")
+    cr = W.crystal(1024, dk_per_mm=0.7)
+    ins = dict(crystal=cr, cavity=W.cavity(), fields=W.initial_fields(1024, 2e6, 9),
+               pump_in=np.full(1024, 2e6 + 0j))
+    with B.Opo([ins], 10) as a:
+        a.ssfm_propagate(10, 0.25)
+        ref = a.get_fields()
+    with B.Opo([ins], 10) as b:
+        b.ssfm_propagate(6, 0.25)
+        ck = b.checkpoint()
+    assert ck["z"] == pytest.approx(1.5)
+    with B.Opo([ins], 10) as c:
+        c.restore(ck)
+        c.ssfm_propagate(4, 0.25)
+        assert _same(c.get_fields(), ref)
+    ref_o = oracle.ssfm_pass(cr, ins["fields"], 10, 0.25)
+    assert np.linalg.norm(ref - ref_o) / np.linalg.norm(ref_o) <= 1e-4
+
+
+def test_set_progress_rejects_bad_arguments():
+    w = W.config("sro_cw", nt=64, nz=3)
+    with B.from_workload(w) as h:
+        for rt, z, hist in [(-1, 0.0, None), (2, 0.0, None), (0, -1.0, None), (0, float("nan"), None)]:
+            with pytest.raises(B.OpoError) as ei:
+                h._lib and B._check(h._lib.opo_set_progress(h.h, rt, z, hist))
+            assert ei.value.code == B.OPO_EINVAL
+
+
+def test_adaptive_non_finite_fields_spend_the_budget():
+    """An instance whose fields hold a NaN is rejected at every attempt (its error ratio
+    is not a number) and keeps its fields; the other instance of the batch runs to the
+    end as in the oracle."""
+    say("adaptive NaN")
+    cr = W.crystal(512, t_window_ps=20.0, deff=40.0, dk_per_mm=0.8, length_mm=2.0)
+    t = W.time_grid(512, 20.0)
+    a = np.stack([2e6 * np.exp(-t * t / 8.0) + 0j, 2e5 * np.exp(-(t - 1.0) ** 2 / 2.0) + W.noise(512, 1e3, 3),
+                  W.noise(512, 1e4, 4)])
+    good = dict(crystal=cr, cavity=W.cavity(), fields=a, pump_in=a[0].copy())
+    bad_a = a.copy()
+    bad_a[2, 100] = np.nan
+    bad = dict(good, fields=bad_a)
+    L, tol, dz0, budget = 2.0, 1e-6, 0.1, 40
+    ref, ra, rr = oracle.propagate_adaptive(cr, a, L, tol, dz0, max_steps=budget)
+    _, ba, br = oracle.propagate_adaptive(cr, bad_a, L, tol, dz0, max_steps=budget, budget_ok=True)
+    assert (ba, br) == (0, budget)
+    with B.Opo([good, bad], 40, precision="f64") as h:
+        acc = np.zeros(2, np.int32)
+        rej = np.zeros(2, np.int32)
+        zend = np.zeros(2)
+        rc = h._lib.ssfm_propagate_adaptive(h.h, L, tol, dz0, budget, acc.ctypes.data, rej.ctypes.data,
+                                            zend.ctypes.data)
+        assert rc == B.OPO_ESTEPS
+        assert (acc[1], rej[1]) == (0, budget) and zend[1] == 0.0
+        assert (acc[0], rej[0]) == (ra, rr) and zend[0] == L
+        assert _same(h.get_fields(1), bad_a)
+        got = h.get_fields(0)
+    for x in range(3):
+        assert np.linalg.norm(got[x] - ref[x]) / np.linalg.norm(ref[x]) <= 1e-11

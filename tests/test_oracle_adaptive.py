@@ -120,3 +120,25 @@ def test_zero_length_and_order_check():
     assert (acc, rej) == (0, 0) and np.array_equal(out, a)
     with pytest.raises(ValueError):
         oracle.propagate_adaptive(dict(cr, order=4), a, 1.0, 1e-6, 0.1)
+
+
+def test_non_finite_error_rejects():
+    """A d that is not a number rejects the attempt (an overflowed step would be retried
+    smaller); fields that are not finite never pass, so the budget ends the run with the
+    fields as they came in. Fields that are zero everywhere (0/0) keep every attempt at an
+    unchanged step: ceil(L / dz0) of them."""
+    cr, a = _case()
+    bad = a.copy()
+    bad[1, 5] = np.nan
+    out, acc, rej = oracle.propagate_adaptive(cr, bad, 1.0, 1e-6, 0.1, max_steps=7, budget_ok=True)
+    assert (acc, rej) == (0, 7)
+    assert np.array_equal(out, bad, equal_nan=True)
+    with pytest.raises(RuntimeError):
+        oracle.propagate_adaptive(cr, bad, 1.0, 1e-6, 0.1, max_steps=7)
+    inf = a.copy()
+    inf[0, 0] = np.inf
+    out, acc, rej = oracle.propagate_adaptive(cr, inf, 1.0, 1e-6, 0.1, max_steps=5, budget_ok=True)
+    assert (acc, rej) == (0, 5)
+    zero = np.zeros_like(a)
+    out, acc, rej = oracle.propagate_adaptive(cr, zero, 1.0, 1e-6, 0.3)
+    assert (acc, rej) == (4, 0) and np.all(out == 0)
