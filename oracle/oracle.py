@@ -14,7 +14,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "opo_oracle.c")
-_LIB = os.path.join(_HERE, "libopo_oracle.so")
+_LIB_PLAIN = os.path.join(_HERE, "libopo_oracle.so")
+_LIB_SANITIZE = os.path.join(_HERE, "libopo_oracle_sanitize.so")
+# ORACLE_LIB=sanitize loads the AddressSanitizer/UBSan build (CPU test runs only)
+_LIB = _LIB_SANITIZE if os.environ.get("ORACLE_LIB") == "sanitize" else _LIB_PLAIN
 
 _c3 = ctypes.c_double * 3
 _i3 = ctypes.c_int * 3
@@ -79,14 +82,19 @@ class Cavity(ctypes.Structure):
         return c
 
 
-def build(force=False):
-    """Compile the oracle with gcc (strict IEEE: no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
+def build(force=False, sanitize=False):
+    """Compile the oracle with gcc (strict IEEE: no fast-math). sanitize: with
+    AddressSanitizer and UndefinedBehaviorSanitizer into libopo_oracle_sanitize.so, which
+    ORACLE_LIB selects (the process must preload gcc's libasan)."""
+    lib = _LIB_SANITIZE if sanitize else _LIB_PLAIN
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+        tmp = lib + ".tmp%d" % os.getpid()
+        extra = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                 "-fno-sanitize-recover=all"] if sanitize else []
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-                               "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+                               "-ffp-contract=off"] + extra + [_SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, lib)
+    return lib
 
 
 _lib = None
@@ -95,7 +103,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        build()
+        build(sanitize=_LIB == _LIB_SANITIZE)
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         lib.ora_fft.argtypes = [P, ctypes.c_int, ctypes.c_int]

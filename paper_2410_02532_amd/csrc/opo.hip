@@ -282,6 +282,47 @@ static void set_crystal(InstDesc &d, const opo_fields_t &f, const opo_crystal_t 
                      (0.5 * f.n[x] * 8.8541878128e-12 * 299792458.0) * 1e-3;
 }
 
+// Descriptor of one instance from its inputs and four-step split: everything
+// but the offsets into the batch's buffers (state, input pump, tables, tiles).
+static void fill_desc(InstDesc &d, const opo_fields_t &f, const opo_crystal_t &c, const opo_cavity_t &k,
+                      const Plan &p)
+{
+    std::memset(&d, 0, sizeof(d));
+    d.nt = f.nt;
+    d.log2nt = ilog2(d.nt);
+    d.n1 = 1 << p.log2n1;
+    d.log2n1 = p.log2n1;
+    d.n2 = 1 << p.log2n2;
+    d.log2n2 = p.log2n2;
+    d.cols = p.cols;
+    d.rows = p.rows;
+    d.nf = nfields(f);
+    d.pump_off = -1;
+    d.pump_windows = f.pump_windows > 1 ? f.pump_windows : 1;
+    d.tiles_a = (d.n1 + d.cols - 1) / d.cols;
+    d.tiles_b = d.nf * ((d.n2 + d.rows - 1) / d.rows);
+    for (int x = 0; x < d.nf; ++x) {
+        if (k.resonant[x]) d.res_mask |= 1 << x;
+        if (k.gdd_on[x] && k.gdd_fs2 != 0.0) d.gdd_mask |= 1 << x;
+        if (k.eom_on[x] && k.eom_beta != 0.0) d.eom_mask |= 1 << x;
+    }
+    const double T = f.t_window_ps;
+    set_crystal(d, f, c);
+    for (int x = 0; x < 3; ++x) {
+        const double sr = std::sqrt(k.refl[x]);
+        d.mirror[x][0] = sr * std::cos(k.delta_rad[x]);
+        d.mirror[x][1] = sr * std::sin(k.delta_rad[x]);
+    }
+    d.gdd_rev = kPi * k.gdd_fs2 * 1e-6 / (T * T);   // gamma w^2/2 / (2 pi)
+    d.eom_beta = k.eom_beta;
+    d.eom_rev0 = -0.5 * T * k.eom_fpm_thz;          // f t_0
+    d.eom_rev_step = k.eom_fpm_thz * T / d.nt;       // f dt
+    d.pump_cw[0] = f.pump_cw[0];
+    d.pump_cw[1] = f.pump_cw[1];
+    // a resonant pump: the input couples in through the pump mirror
+    d.inject = k.resonant[0] ? std::sqrt(1.0 - k.refl[0]) : 0.0;
+}
+
 static int validate(int n, int K, const opo_fields_t *f, const opo_crystal_t *c, const opo_cavity_t *k,
                     int precision, double step_scale)
 {
@@ -713,27 +754,14 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     h->inst.resize(n);
     for (int i = 0; i < n; ++i) {
         InstDesc &d = h->inst[i];
-        std::memset(&d, 0, sizeof(d));
         const Plan p = make_plan(f[i].nt, opt.precision, opt.col_log2);
-        d.nt = f[i].nt;
-        d.log2nt = ilog2(d.nt);
-        d.n1 = 1 << p.log2n1;
-        d.log2n1 = p.log2n1;
-        d.n2 = 1 << p.log2n2;
-        d.log2n2 = p.log2n2;
-        d.cols = p.cols;
-        d.rows = p.rows;
-        d.nf = nfields(f[i]);
+        fill_desc(d, f[i], c[i * K], k[i], p);
         d.off = off;
         off += static_cast<long long>(d.nf) * d.nt;
-        d.pump_off = -1;
-        d.pump_windows = f[i].pump_windows > 1 ? f[i].pump_windows : 1;
         if (f[i].pump_in) {
             d.pump_off = pump_elems;
             pump_elems += static_cast<long long>(d.nt) * d.pump_windows;
         }
-        d.tiles_a = (d.n1 + d.cols - 1) / d.cols;
-        d.tiles_b = d.nf * ((d.n2 + d.rows - 1) / d.rows);
         // LDS of a tile: nf fields of `cols` columns, or `rows` rows
         const bool seq = opt.precision == OPO_F64 ? col_seq_lds<double>(p.log2n2) : col_seq_lds<float>(p.log2n2);
         max_a = std::max(max_a, static_cast<size_t>(seq ? 1 : d.nf) * d.cols * d.n2);
@@ -755,33 +783,8 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
             d.w4_off = it->second;
         }
 
-        int res = 0, gdd = 0, eom = 0;
-        for (int x = 0; x < d.nf; ++x) {
-            if (k[i].resonant[x]) res |= 1 << x;
-            if (k[i].gdd_on[x] && k[i].gdd_fs2 != 0.0) gdd |= 1 << x;
-            if (k[i].eom_on[x] && k[i].eom_beta != 0.0) eom |= 1 << x;
-        }
-        d.res_mask = res;
-        d.gdd_mask = gdd;
-        d.eom_mask = eom;
-        h->any_gdd |= gdd != 0;
-        h->any_eom |= eom != 0;
-
-        const double T = f[i].t_window_ps;
-        set_crystal(d, f[i], c[i * K]);
-        for (int x = 0; x < 3; ++x) {
-            const double sr = std::sqrt(k[i].refl[x]);
-            d.mirror[x][0] = sr * std::cos(k[i].delta_rad[x]);
-            d.mirror[x][1] = sr * std::sin(k[i].delta_rad[x]);
-        }
-        d.gdd_rev = kPi * k[i].gdd_fs2 * 1e-6 / (T * T);   // gamma w^2/2 / (2 pi)
-        d.eom_beta = k[i].eom_beta;
-        d.eom_rev0 = -0.5 * T * k[i].eom_fpm_thz;             // f t_0
-        d.eom_rev_step = k[i].eom_fpm_thz * T / d.nt;          // f dt
-        d.pump_cw[0] = f[i].pump_cw[0];
-        d.pump_cw[1] = f[i].pump_cw[1];
-        // a resonant pump: the input couples in through the pump mirror
-        d.inject = k[i].resonant[0] ? std::sqrt(1.0 - k[i].refl[0]) : 0.0;
+        h->any_gdd |= d.gdd_mask != 0;
+        h->any_eom |= d.eom_mask != 0;
     }
 
     // ---- halves of a batch for the mixed schedule: instances are dealt to

@@ -203,7 +203,7 @@ def config(name, **over):
                              fields=initial_fields(nt, ap0, 1000 + b),
                              pump_in=np.full(nt, ap0 + 0j)))
         return dict(name=name, instances=inst, nz=over.get("nz", 100),
-                    n_rt=over.get("n_rt", 500), precision="f32")
+                    n_rt=over.get("n_rt", 500), precision="f32", levels=levels.tolist())
     if name == "degenerate_cw":        # two-wave degenerate CW oscillator, Nt = 2^14
         nt = over.get("nt", 1 << 14)
         level = over.get("level", 3.0)

@@ -26,7 +26,7 @@ SAMPLES = 64
 
 
 def _cases():
-    return {
+    c = {
         # CW SRO at its full size: Nt = 2^14, Nz = 100, 2000 round trips, 3x threshold
         "sro_cw_2000rt": dict(workload="sro_cw", over={}, n_rt=2000, every=50),
         # fast-growing SRO (6x threshold, R = 0.90) that saturates: the depleted regime
@@ -40,6 +40,18 @@ def _cases():
         # same with GDD -2000 fs^2 (instance 8)
         "dro_large_inst8": dict(workload="dro_large", over=dict(count=16), inst=8, n_rt=3, every=1),
     }
+    # the benchmarked batched sweep over its 500 round trips: per size class, the instance
+    # with the highest pump level (the fastest build-up)
+    for nt in (4096, 8192, 16384, 32768, 65536):
+        c["batched_sweep_nt%d" % nt] = dict(workload="batched_sweep", over={}, inst=_sweep_pick(nt),
+                                           n_rt=500, every=10)
+    return c
+
+
+def _sweep_pick(nt):
+    w = W.config("batched_sweep")
+    cand = [b for b, ins in enumerate(w["instances"]) if ins["crystal"]["nt"] == nt]
+    return max(cand, key=lambda b: w["levels"][b])
 
 
 def _instance(case):

@@ -149,3 +149,57 @@ def test_batched_sweep_full_size_sampled():
         for x in range(3):
             assert np.linalg.norm(a[x] - ref[x]) / np.linalg.norm(ref[x]) <= 2e-4, (i, x)
             assert np.max(_rel(e[:, x], e_ref[:, x])) <= 1e-3
+
+
+def _sweep_golden_picks(w):
+    """Per size class, the instance with the highest pump level, as the stored runs."""
+    out = {}
+    for nt in (4096, 8192, 16384, 32768, 65536):
+        cand = [b for b, ins in enumerate(w["instances"]) if ins["crystal"]["nt"] == nt]
+        out[max(cand, key=lambda b: w["levels"][b])] = nt
+    return out
+
+
+def test_batched_sweep_500_round_trips():
+    """The benchmarked batch as benchmarked (256 instances, FP32, mixed launches from a
+    graph) over its 500 round trips: per size class, the highest-pump instance against a
+    stored oracle run (energies every 10 round trips within 1e-3), and every instance's
+    energies against the same batch in FP64 on the GPU (whose per-pass parity with the
+    oracle is pinned elsewhere) within 1e-3 over all 500 round trips."""
+    w = W.config("batched_sweep")
+    picks = _sweep_golden_picks(w)
+    assert len(picks) == 5
+    say("batched sweep 256, 500 RT f32")
+    with B.from_workload(w, precision="f32") as h:
+        h.cavity_roundtrip(500)
+        e32 = [h.energy_history(i) for i in range(len(w["instances"]))]
+    for i, nt in picks.items():
+        g = golden("batched_sweep_nt%d" % nt)
+        assert g["instance"] == i and g["n_rt"] == 500
+        _check_energies(e32[i], g, 1e-3)
+    say("batched sweep 256, 500 RT f64")
+    with B.from_workload(w, precision="f64") as h:
+        h.cavity_roundtrip(500)
+        e64 = [h.energy_history(i) for i in range(len(w["instances"]))]
+    worst = 0.0
+    for i in range(len(w["instances"])):
+        assert e32[i].shape == (500, 3)
+        worst = max(worst, float(np.max(_rel(e32[i], e64[i]))))
+    say("f32 vs f64 worst relative energy error over 256 instances x 500 RT: %.3g" % worst)
+    assert worst <= 1e-3
+
+
+def test_dro_batch_reduced_size_f32_vs_f64():
+    """The 16-instance doubly resonant batch with GDD and EOM beyond the three stored oracle
+    round trips of its full size, at 2^18 points (the FP64 path ends at 2^19): FP32 against
+    FP64 on the GPU over 100 round trips, every instance."""
+    w = W.config("dro_large", nt=1 << 18)
+    n = 100
+    out = {}
+    for prec in ("f32", "f64"):
+        say("DRO 16 x 2^18, %d RT %s" % (n, prec))
+        with B.from_workload(w, precision=prec) as h:
+            h.cavity_roundtrip(n)
+            out[prec] = [h.energy_history(i) for i in range(16)]
+    for i in range(16):
+        assert np.max(_rel(out["f32"][i], out["f64"][i])) <= 1e-3, i

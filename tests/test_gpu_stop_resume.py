@@ -89,7 +89,7 @@ def test_overflow_stops_at_the_last_finite_round_trip(graph, gdd):
             h.cavity_roundtrip(400)
         assert ei.value.code == B.OPO_ENONFINITE
         m, z = h.progress()
-        assert 5 < m < 400 and z == 0.0
+        assert 0 < m < 400 and z == 0.0
         f, e = h.get_fields(), h.energy_history()
     assert e.shape == (m, 3) and np.all(np.isfinite(e))
     assert np.all(np.isfinite(f))
