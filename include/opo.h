@@ -238,6 +238,26 @@ int opo_sync(opo_t *h);
 int opo_get_fields(opo_t *h, int32_t inst, int32_t field, int32_t domain, double *out);
 int opo_set_fields(opo_t *h, int32_t inst, int32_t field, const double *in);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the spectrum of every
+ * field of instance `inst`, written to caller device memory without any
+ * allocation. out: device pointer to n_fields * nt complex values at the
+ * handle's precision (complex64 for OPO_F32, complex128 for OPO_F64), field-
+ * major, bin k of field x at out[x * nt + k] in natural bin order: the
+ * unnormalized DFT sum_j A(t_j) e^{-2 pi i jk/nt}, the same values, bit for
+ * bit, as opo_get_fields with domain 1. The caller owns out and keeps it alive
+ * until the stream has passed the call. Asynchronous on the handle's stream (no
+ * synchronization); the fields are not changed.
+ * Scratch: a fixed 16 MiB device array that each GPU the library runs on
+ * holds until the process ends; the call takes its device address on the
+ * first use on a device. An instance needing more than 16 MiB - 16 KiB
+ * (n_fields * nt * 8 bytes in FP32, * 16 in FP64: up to 3 x 2^19 points in
+ * FP32, 3 x 2^18 in FP64) is rejected with OPO_EINVAL. Every call on a GPU
+ * shares that array and overwrites it: calls that overlap on one GPU (two
+ * handles on different streams, or two threads) race, so serialize them.
+ * OPO_EINVAL for a bad instance or a NULL out. */
+int opo_get_spectrum_noalloc(opo_t *h, int32_t inst, void *out);
+
 /* Checkpoint and resume (the per-round-trip save of Sec. 4.1). A run is
  * resumed bit for bit by a handle created with the same inputs and options:
  * set every field with opo_set_fields, then opo_set_progress with what

@@ -120,4 +120,18 @@ __global__ void set_counter(int *counter, int slot, int rt, int clear_flags)
     }
 }
 
+__global__ __launch_bounds__(kThreads) void spectrum_prep(const InstDesc *inst, int i, InstDesc *desc,
+                                                          int *counter, int *map, int map_len)
+{
+    if (threadIdx.x == 0) {
+        InstDesc d = inst[i];
+        d.off = 0;
+        d.tile_a0 = 0;
+        d.tile_b0 = 0;
+        *desc = d;
+    }
+    if (threadIdx.x < 4) counter[threadIdx.x] = 0;
+    for (int q = threadIdx.x; q < map_len; q += kThreads) map[q] = 0;
+}
+
 } // namespace opo

@@ -20,7 +20,8 @@
     DECL __global__ void adapt_begin<R>(const InstDesc *, const AdaptState *, int, cplx<R> *,      \
                                         const cplx<R> *, const cplx<R> *, Phasor<R> *);            \
     DECL __global__ void adapt_error<R>(const InstDesc *, const AdaptState *, int, const cplx<R> *, \
-                                        const cplx<R> *, double *);
+                                        const cplx<R> *, double *);                                \
+    DECL __global__ void spectrum_order<R>(const InstDesc *, const cplx<R> *, cplx<R> *);
 
 #define OPO_PASS_KERNELS_F32(DECL)                                                                 \
     OPO_PASS_KERNELS_COMMON(DECL, float)                                                           \

@@ -199,7 +199,7 @@ struct opo_s {
     bool any_gdd = false, any_eom = false;
     int use_graph = 1;
     hipGraphExec_t graph = nullptr;
-    void *scratch = nullptr;         // spectrum read-out
+    void *spec_buf = nullptr;        // spectrum read-out (opo_get_fields, domain 1)
     // adaptive step: coarse and fine copies of the state, per-instance
     // propagator tables (coarse and fine step), control state, error partials
     void *a_uc = nullptr, *a_uf = nullptr, *a_tab = nullptr;
@@ -437,7 +437,7 @@ static void release(opo_t *h)
     if (h->a_graph) (void)hipGraphExecDestroy(h->a_graph);
     if (h->own_state && h->state) (void)hipFree(h->state);
     void *bufs[] = {h->d_w4tab, h->pump, h->d_inst, h->d_tile_a, h->d_tile_b, h->d_tw, h->d_disp, h->d_map[0], h->d_map[1],
-                    h->d_partial, h->d_hist, h->d_counter, h->scratch, h->d_record, h->d_snap,
+                    h->d_partial, h->d_hist, h->d_counter, h->spec_buf, h->d_record, h->d_snap,
                     h->a_uc, h->a_uf, h->a_tab, h->d_actl, h->d_apart};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -1311,16 +1311,16 @@ template <typename R> static int roundtrip_impl(opo_t *h, int n_rt)
 template <typename R> static int spectrum_impl(opo_t *h, int inst, int field, double *out)
 {
     const InstDesc &d = h->inst[inst];
-    if (!h->scratch) {
-        if (hipMalloc(&h->scratch, h->state_bytes) != hipSuccess)
-            return fail(OPO_ENOMEM, "hipMalloc of the spectrum scratch failed");
+    if (!h->spec_buf) {
+        if (hipMalloc(&h->spec_buf, h->state_bytes) != hipSuccess)
+            return fail(OPO_ENOMEM, "hipMalloc of the spectrum buffer failed");
     }
-    HIP_TRY(hipMemcpyAsync(h->scratch, h->state, h->state_bytes, hipMemcpyDeviceToDevice, h->stream));
-    StepArgs<R> a = base_args<R>(h, h->scratch);
+    HIP_TRY(hipMemcpyAsync(h->spec_buf, h->state, h->state_bytes, hipMemcpyDeviceToDevice, h->stream));
+    StepArgs<R> a = base_args<R>(h, h->spec_buf);
     HIP_TRY(launch_a<R>(h, a, A_FWD, 0));
     HIP_TRY(launch_b<R>(h, a, B_FWD_ONLY));
     std::vector<double> tmp(2 * static_cast<size_t>(d.nt));
-    const char *src = static_cast<const char *>(h->scratch) + (d.off + static_cast<long long>(field) * d.nt) * h->elem;
+    const char *src = static_cast<const char *>(h->spec_buf) + (d.off + static_cast<long long>(field) * d.nt) * h->elem;
     HIP_TRY(state_to_host<R>(tmp.data(), src, d.nt, h->stream));
     // position k2*n1 + k1 holds bin k2 + n2*k1
     for (int k2 = 0; k2 < d.n2; ++k2)
@@ -1330,6 +1330,98 @@ template <typename R> static int spectrum_impl(opo_t *h, int inst, int field, do
             out[2 * bin] = tmp[2 * pos];
             out[2 * bin + 1] = tmp[2 * pos + 1];
         }
+    return OPO_OK;
+}
+
+// ---- spectrum read-out without allocation. Scratch lives in a fixed device
+// array (each GPU the library runs on holds its own copy until the process
+// ends): the descriptor of a one-instance batch, its tile -> instance map and
+// counters, then the instance's fields as the column and row passes leave them.
+// Calls on one GPU share the array: calls that overlap there race.
+static constexpr size_t kNoAllocBytes = size_t(16) << 20;
+static constexpr size_t kNoAllocCounterOff = 1024;     // 4 ints
+static constexpr size_t kNoAllocMapOff = 2048;         // tile -> instance map
+static constexpr size_t kNoAllocMapInts = 3584;
+static constexpr size_t kNoAllocFieldOff = 16384;      // fields, 256-byte aligned
+static_assert(sizeof(InstDesc) <= kNoAllocCounterOff, "descriptor does not fit its scratch slot");
+static_assert(kNoAllocMapOff + kNoAllocMapInts * sizeof(int) <= kNoAllocFieldOff, "map overlaps the fields");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Device address of `scratch` per device, taken once with that device current
+// (in host code the array's name is only a stand-in for it).
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char *> g_scratch_ptr;
+
+static int scratch_on_device(int device, unsigned char **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it == g_scratch_ptr.end()) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || p == nullptr)
+            return fail(OPO_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        it = g_scratch_ptr.emplace(device, static_cast<unsigned char *>(p)).first;
+    }
+    *out = it->second;
+    return OPO_OK;
+}
+
+// The column pass (forward column FFT and four-step twiddle) loads instance
+// `inst` from the state and stores into the scratch fields, the row pass
+// finishes the forward transform in place, and spectrum_order writes natural
+// bin order into `out`. The same kernels as the domain-1 read-out of
+// opo_get_fields, on the same tiles, so the values are identical.
+template <typename R> static int spectrum_noalloc_impl(opo_t *h, int inst, void *out)
+{
+    const InstDesc &d = h->inst[inst];
+    const size_t field_bytes = static_cast<size_t>(d.nf) * static_cast<size_t>(d.nt) * sizeof(cplx<R>);
+    const int map_len = std::max(d.tiles_a, d.tiles_b);
+    if (field_bytes > kNoAllocBytes - kNoAllocFieldOff || static_cast<size_t>(map_len) > kNoAllocMapInts)
+        return fail(OPO_EINVAL, "instance " + std::to_string(inst) + " needs " + std::to_string(field_bytes) +
+                                    " bytes of scratch; the no-allocation read-out holds at most " +
+                                    std::to_string(kNoAllocBytes - kNoAllocFieldOff));
+    unsigned char *base = nullptr;
+    int rc = scratch_on_device(h->device, &base);
+    if (rc) return rc;
+    InstDesc *desc = reinterpret_cast<InstDesc *>(base);
+    int *counter = reinterpret_cast<int *>(base + kNoAllocCounterOff);
+    int *map = reinterpret_cast<int *>(base + kNoAllocMapOff);
+    cplx<R> *fields = reinterpret_cast<cplx<R> *>(base + kNoAllocFieldOff);
+
+    spectrum_prep<<<1, kThreads, 0, h->stream>>>(h->d_inst, inst, desc, counter, map, map_len);
+    HIP_TRY(hipGetLastError());
+    StepArgs<R> a{};
+    a.inst = desc;
+    a.tile_inst = map;
+    a.state = fields;
+    a.src = static_cast<const cplx<R> *>(h->state) + d.off;
+    a.tw = static_cast<const Phasor<R> *>(h->d_tw);
+    a.w4tab = static_cast<const Phasor<R> *>(h->d_w4tab);
+    a.disp = static_cast<const Phasor<R> *>(h->d_disp);
+    a.counter = counter;
+    a.nz = h->nz;
+    a.flags = A_FWD;
+    a.tile0 = 0;
+    a.tile_count = d.tiles_a;
+    {
+        void *args[] = {&a};
+        HIP_TRY(hipLaunchKernel(column_fn<R>(range_of(kColRanges, d.log2n2), d.nf), dim3(d.tiles_a),
+                                dim3(kThreads), args, h->lds_a, h->stream));
+    }
+    a.src = nullptr;
+    a.flags = B_FWD_ONLY;
+    a.tile_count = d.tiles_b;
+    {
+        void *args[] = {&a};
+        HIP_TRY(hipLaunchKernel(row_fn<R>(range_of(kRowRanges, d.log2n1)), dim3(d.tiles_b), dim3(kThreads), args,
+                                h->lds_b, h->stream));
+    }
+    const long long n = static_cast<long long>(d.nf) * d.nt;
+    const int blocks = static_cast<int>(std::min<long long>((n + kThreads - 1) / kThreads, 4096));
+    spectrum_order<R><<<blocks, kThreads, 0, h->stream>>>(desc, fields, static_cast<cplx<R> *>(out));
+    HIP_TRY(hipGetLastError());
     return OPO_OK;
 }
 
@@ -1458,6 +1550,19 @@ int opo_set_fields(opo_t *h, int32_t inst, int32_t field, const double *in)
         return OPO_OK;
     } catch (...) {
         return fail(OPO_ENOMEM, "host allocation failed");
+    }
+}
+
+int opo_get_spectrum_noalloc(opo_t *h, int32_t inst, void *out)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    if (inst < 0 || inst >= h->n_inst || !out) return fail(OPO_EINVAL, "bad instance or output pointer");
+    try {
+        return h->precision == OPO_F64 ? spectrum_noalloc_impl<double>(h, inst, out)
+                                       : spectrum_noalloc_impl<float>(h, inst, out);
+    } catch (...) {
+        return fail(OPO_EDEVICE, "unexpected exception in opo_get_spectrum_noalloc");
     }
 }
 

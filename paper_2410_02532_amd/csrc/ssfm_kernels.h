@@ -906,4 +906,29 @@ __global__ __launch_bounds__(kThreads) void energy_reduce(const InstDesc *inst, 
 // counter[0] = slot; counter[1] = rt unless rt < 0; clear_flags: counter[2] = counter[3] = 0.
 __global__ void set_counter(int *counter, int slot, int rt, int clear_flags);
 
+// ------------------------------------------------------------------------
+// Spectrum read-out into caller memory without allocating: the column and row
+// passes run on a one-instance batch held in a fixed scratch area. spectrum_prep
+// writes there the descriptor of instance i as that batch's only instance
+// (fields at offset 0, tiles counted from 0), a zeroed tile -> instance map of
+// map_len entries and zeroed counters (one workgroup).
+__global__ __launch_bounds__(kThreads) void spectrum_prep(const InstDesc *inst, int i, InstDesc *desc,
+                                                          int *counter, int *map, int map_len);
+
+// out[f nt + k] = bin k of field f, from the row-pass layout, where bin
+// k = k2 + n2 k1 sits at position k2 n1 + k1 of its field.
+template <typename R>
+__global__ __launch_bounds__(kThreads) void spectrum_order(const InstDesc *desc, const cplx<R> *src, cplx<R> *out)
+{
+    const InstDesc &d = *desc;
+    const long long n = static_cast<long long>(d.nf) * d.nt;
+    for (long long q = blockIdx.x * static_cast<long long>(kThreads) + threadIdx.x; q < n;
+         q += static_cast<long long>(gridDim.x) * kThreads) {
+        const long long f = q >> d.log2nt;
+        const int k = static_cast<int>(q & (d.nt - 1));
+        const int k2 = k & (d.n2 - 1), k1 = k >> d.log2n2;
+        out[q] = src[(f << d.log2nt) + (static_cast<long long>(k2) << d.log2n1) + k1];
+    }
+}
+
 } // namespace opo

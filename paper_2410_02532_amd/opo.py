@@ -24,7 +24,7 @@ EXPORTS = ("opo_state_bytes", "opo_init", "opo_init_batch", "ssfm_propagate", "s
            "opo_get_energy_history",
            "opo_get_power_history",
            "opo_get_record", "opo_get_grid", "opo_kernel_times", "opo_info", "opo_destroy",
-           "opo_last_error")
+           "opo_last_error", "opo_get_spectrum_noalloc")
 KERNEL_CLASSES = ("column_pass", "row_pass", "energy_reduce", "mixed_pass")
 
 _d3 = ctypes.c_double * 3
@@ -92,6 +92,7 @@ def load():
     lib.opo_sync.argtypes = [P]
     lib.opo_get_fields.argtypes = [P, I, I, I, P]
     lib.opo_set_fields.argtypes = [P, I, I, P]
+    lib.opo_get_spectrum_noalloc.argtypes = [P, I, P]
     lib.opo_get_progress.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(D)]
     lib.opo_set_progress.argtypes = [P, I, D, P]
     lib.opo_get_energy_history.argtypes = [P, I, P, I, ctypes.POINTER(I)]
@@ -105,7 +106,8 @@ def load():
     lib.opo_last_error.restype = ctypes.c_char_p
     for name in ("opo_init", "opo_init_batch", "ssfm_propagate", "ssfm_propagate_adaptive",
                  "cavity_roundtrip", "opo_sync",
-                 "opo_get_fields", "opo_set_fields", "opo_get_progress", "opo_set_progress",
+                 "opo_get_fields", "opo_set_fields", "opo_get_spectrum_noalloc",
+                 "opo_get_progress", "opo_set_progress",
                  "opo_get_energy_history", "opo_get_record",
                  "opo_get_power_history",
                  "opo_get_grid",
@@ -270,6 +272,17 @@ class Opo:
         for x in range(nf):
             row = np.ascontiguousarray(a[x])
             _check(self._lib.opo_set_fields(self.h, inst, x, row.ctypes.data))
+
+    def spectrum_noalloc(self, out, inst=0):
+        """Spectra of every field of instance inst into the device tensor `out` (nf * nt
+        complex values at the handle's precision, contiguous) through the entry point that
+        allocates nothing; queued on the handle's stream (sync() waits)."""
+        import torch
+        nt, nf = self.nts[inst], self.nfs[inst]
+        want = torch.complex128 if self.precision == OPO_F64 else torch.complex64
+        if out.dtype != want or out.numel() != nf * nt or not out.is_contiguous() or out.device != self._dev:
+            raise ValueError("out must be a contiguous %s tensor of %d values on %s" % (want, nf * nt, self._dev))
+        _check(self._lib.opo_get_spectrum_noalloc(self.h, int(inst), ctypes.c_void_p(out.data_ptr())))
 
     def progress(self):
         """(round trips completed since opo_init, z of the next ssfm_propagate)."""
