@@ -7,10 +7,13 @@ instance of the batch in the same launches) replayed from a hipGraph.
 The default workload is the batched sweep: 256 CW singly resonant OPOs with Nt
 drawn from {2^12 .. 2^16}, pump 1-6x threshold, detuning +-0.5 rad, signal
 R 0.90-0.99, Nz = 100, 500 round trips, complex64 fields with FP64 phase
-arguments and energies, seeded synthetic inputs. Variants reported beside it
-(FP64, one instance at a time, the single 2^14 SRO, the synchronously pumped
-2^18 OPO, the 16 x 2^20 DRO batch, the two-wave sweep, the nanosecond regime and
-the adaptive step) each carry their error against the FP64 oracle.
+arguments and energies, seeded synthetic inputs, the automatic schedule (the
+2^12 instances run resident beside the two-pass launches of the others).
+Variants reported beside it (FP64, one instance at a time, the single 2^14 SRO
+with its automatic and its default split, the synchronously pumped 2^18 OPO,
+the 16 x 2^20 DRO batch, the two-wave sweep, a sweep of 2^10..2^12 grids
+resident and in two passes, the nanosecond regime and the adaptive step) each
+carry their error against the FP64 oracle.
 
 Metric: field-point-steps per second = sum over instances of Nt * Nz * round
 trips / time, with the inputs resident in HBM when the timed region starts.
@@ -95,6 +98,12 @@ def run_gpu(w, steps, warmup, precision, keep=(), **kw):
         dev_s, wall_s = timed_roundtrips(h, steps)
         hist = {i: h.energy_history(i) for i in keep}
     return dev_s, wall_s, hist
+
+
+def plans(w, precision, **kw):
+    """(log2 n1, log2 n2, resident) of every instance under the handle's schedule."""
+    with B.from_workload(w, precision=precision, **kw) as h:
+        return [h.plan(i) for i in range(len(instances_of(w)))]
 
 
 # ------------------------------------------------------------------ errors --
@@ -221,12 +230,14 @@ def roofline(w, precision, n_rt):
     """Roofline of the dominant kernel from per-launch device times (HIP events around every
     launch on the handle's stream, profile option).
 
-    Each column, row or mixed launch carries out half of a z-step for the points it covers
-    (a z-step is a column and a row pass of every instance), so its algorithmic work is half
-    a field-point-step per covered point: 48/2 B (FP32) of HBM traffic and
-    flops_per_unit/2. The line is priced against HBM (the algorithmic minimum of one read
+    Each column, row or mixed launch carries out half of a z-step for the points of the
+    two-pass instances it covers (a z-step is a column and a row pass of every such
+    instance), so its algorithmic work is half a field-point-step per covered point: 48/2 B
+    (FP32) of HBM traffic and flops_per_unit/2. Instances that run resident are not covered
+    by those launches. The line is priced against HBM (the algorithmic minimum of one read
     and one write of every field per z-step); the VALU figures stand beside it."""
     with B.from_workload(w, precision=precision, profile=True) as h:
+        two_pass = [i for i in range(len(instances_of(w))) if not h.plan(i)[2]]
         h.cavity_roundtrip(2)            # warm up
         before = h.kernel_times()
         h.cavity_roundtrip(n_rt)
@@ -234,7 +245,7 @@ def roofline(w, precision, n_rt):
     per = {k: (after[k][0] - before[k][0], after[k][1] - before[k][1]) for k in after}
     dom = max(("column_pass", "row_pass", "mixed_pass"), key=lambda k: per[k][0])
     ms, launches = per[dom]
-    insts = instances_of(w)
+    insts = [instances_of(w)[i] for i in two_pass]
     bytes_per_launch = sum(BYTES_PER_FIELD[precision] * nf_of(i) * i["crystal"]["nt"] for i in insts) / 2
     flops_per_launch = sum(i["crystal"]["nt"] * flops_per_unit(i["crystal"]["nt"], nf_of(i)) for i in insts) / 2
     avg_s = ms / 1e3 / launches
@@ -253,6 +264,7 @@ def roofline(w, precision, n_rt):
                  "frac_nonpacked": round(tflops / VALU_NONPACKED_TFLOPS, 5)},
         "kernel_ms": {k: round(v[0], 3) for k, v in per.items()},
         "launches": {k: v[1] for k, v in per.items()},
+        "instances_covered": len(insts),
     }
 
 
@@ -439,6 +451,10 @@ def main():
             for i in picks_per_size(dsw):
                 jobs.submit(("deg_pass", i), ("pass", "degenerate_sweep", {}, i, None))
                 jobs.submit(("deg_rt", i), ("rt", "degenerate_sweep", {}, i, 3))
+            small = dict(min_log2=10, max_log2=12)
+            for i in picks_per_size(W.config("batched_sweep", **small), by_level=True):
+                jobs.submit(("small_pass", i), ("pass", "batched_sweep", small, i, None))
+                jobs.submit(("small_rt", i), ("rt", "batched_sweep", small, i, 3))
             for i in range(3):
                 jobs.submit(("ns_pass", i), ("pass", "ns_pulsed", {}, i, None))
                 jobs.submit(("ns_rt", i), ("rt", "ns_pulsed", {}, i, 30))
@@ -465,7 +481,9 @@ def main():
         "config": {"workload": name, "instances": len(instances_of(w)),
                    "nt": sorted({ins["crystal"]["nt"] for ins in instances_of(w)}),
                    "nz": w["nz"], "round_trips": steps, "precision": args.precision,
-                   "graph": True, "wall_s": round(wall_s, 4)},
+                   "graph": True, "schedule": "auto",
+                   "resident_instances": sum(p[2] for p in plans(w, args.precision)),
+                   "wall_s": round(wall_s, 4)},
     }
     if not args.no_roofline:
         line["roofline"] = roofline(w, args.precision, min(steps, 100))
@@ -479,10 +497,12 @@ def main():
             var["%s_single_sro_cw_2^14" % prec] = {"value": pt_steps_per_rt(ws) * n / d,
                                                   "round_trips": n, "ms_per_step": d * 1e3 / n,
                                                   "_hist": hs[0]}
-            # the same with columns of 32 (col_log2 option): twice the column
-            # workgroups, each with half the work, for an instance alone
-            d, _, _ = run_gpu(ws, n, 10, prec, col_log2=5)
-            var["%s_single_sro_cw_2^14_col32" % prec] = {"value": pt_steps_per_rt(ws) * n / d,
+            var["%s_single_sro_cw_2^14" % prec]["split_log2_n1_n2"] = plans(ws, prec)[0][:2]
+            # the same on the default split (columns of 64): the automatic schedule of an
+            # instance alone takes columns of 32 (twice the column workgroups, each with
+            # half the work)
+            d, _, _ = run_gpu(ws, n, 10, prec, schedule="two_pass")
+            var["%s_single_sro_cw_2^14_n2_64" % prec] = {"value": pt_steps_per_rt(ws) * n / d,
                                                         "round_trips": n, "ms_per_step": d * 1e3 / n}
         # the headline workload one instance at a time (a handle per instance, same
         # kernels): the batching gain on the same work
@@ -520,6 +540,17 @@ def main():
         var["f32_degenerate_sweep"] = {"value": pt_steps_per_rt(ws) * n / d, "round_trips": n,
                                        "ms_per_step": d * 1e3 / n, "instances": len(ws["instances"]),
                                        "fields": 2, "_hist": hs}
+        # the paper's small grids: 256 instances of 2^10..2^12 points, where every instance
+        # runs resident (one workgroup per instance for the whole round trip) under the
+        # automatic schedule, against the same batch on two passes per z-step
+        ws = W.config("batched_sweep", min_log2=10, max_log2=12)
+        n = 100
+        d, _, hs = run_gpu(ws, n, 5, "f32", keep=picks_per_size(ws, by_level=True))
+        d2, _, _ = run_gpu(ws, n, 5, "f32", schedule="two_pass")
+        var["f32_small_sweep_2^10..2^12"] = {
+            "value": pt_steps_per_rt(ws) * n / d, "round_trips": n, "ms_per_step": d * 1e3 / n,
+            "instances": len(ws["instances"]), "resident_instances": sum(p[2] for p in plans(ws, "f32")),
+            "two_pass_value": pt_steps_per_rt(ws) * n / d2, "_hist": hs}
         # nanosecond regime: 10 ns pulses read one window per round trip, with the
         # per-round-trip record of the fields leaving the crystal
         ws = W.config("ns_pulsed")
@@ -564,8 +595,8 @@ def main():
                 v = var["%s_single_sro_cw_2^14" % prec]
                 v["pass_rel_l2"] = rel_l2_max(gpu_pass([ws], ws["nz"], prec)[0], sro_ref)
                 v["long_run"] = golden_error(v.pop("_hist"), golden("sro_cw_2000rt"))
-                var["%s_single_sro_cw_2^14_col32" % prec]["pass_rel_l2"] = rel_l2_max(
-                    gpu_pass([ws], ws["nz"], prec, col_log2=5)[0], sro_ref)
+                var["%s_single_sro_cw_2^14_n2_64" % prec]["pass_rel_l2"] = rel_l2_max(
+                    gpu_pass([ws], ws["nz"], prec, schedule="two_pass")[0], sro_ref)
             v = var["f64_%s" % name]
             hs = v.pop("_hist")
             v["pass_rel_l2"] = max(rel_l2_max(g, r) for g, r in zip(
@@ -594,6 +625,15 @@ def main():
             gotd = gpu_pass([ws["instances"][i] for i in dp], ws["nz"], "f32")
             v["pass_rel_l2"] = max(rel_l2_max(g, jobs.get(("deg_pass", i))) for g, i in zip(gotd, dp))
             ee = [energy_errors(hs[i], jobs.get(("deg_rt", i)), [0, 1, 2]) for i in dp]
+            v["short_run"] = {"round_trips": 3, "signal_power_rel": max(x[0] for x in ee),
+                              "energy_rel_all_fields": max(x[1] for x in ee)}
+            ws = W.config("batched_sweep", min_log2=10, max_log2=12)
+            v = var["f32_small_sweep_2^10..2^12"]
+            hs = v.pop("_hist")
+            sp = picks_per_size(ws, by_level=True)
+            gots = gpu_pass([ws["instances"][i] for i in sp], ws["nz"], "f32")   # a batch: resident
+            v["pass_rel_l2"] = max(rel_l2_max(g, jobs.get(("small_pass", i))) for g, i in zip(gots, sp))
+            ee = [energy_errors(hs[i], jobs.get(("small_rt", i)), [0, 1, 2]) for i in sp]
             v["short_run"] = {"round_trips": 3, "signal_power_rel": max(x[0] for x in ee),
                               "energy_rel_all_fields": max(x[1] for x in ee)}
             ws = W.config("ns_pulsed")

@@ -130,15 +130,31 @@ typedef struct {
                                allocates it                                       */
     uint64_t state_bytes;   /* size of *state                                     */
     int32_t col_log2;       /* four-step split nt = n1 * n2 (Sec. 2.2 FFTs): log2 n2
-                               for instances of nt > 2^10, 0 = automatic (n2 = 64
-                               from 2^13 up to the longest rows). 5 (n2 = 32)
-                               gives a single instance of 2^13..2^17 twice the
-                               column workgroups with half the work each: faster
-                               alone (2^14 FP32 +15 %), slower in a large batch.
-                               Clamped to n2 <= n1 and n1 <= 4096 (FP32) or 2048
-                               (FP64). Results differ from another split by
-                               rounding only. 0 or 4..8, else OPO_EINVAL          */
-    int32_t reserved0;      /* must be 0                                          */
+                               for instances of nt > 2^10, 0 = the schedule's
+                               split (schedule 0) or the default (n2 = 64 from
+                               2^13 up to the longest rows). 5 (n2 = 32) gives a
+                               single instance of 2^13..2^17 twice the column
+                               workgroups with half the work each: faster alone,
+                               slower in a large batch. Clamped to n2 <= n1 and
+                               n1 <= 4096 (FP32) or 2048 (FP64). Results differ
+                               from another split by rounding only. 0 or 4..8,
+                               else OPO_EINVAL                                    */
+    int32_t schedule;       /* how fixed-step passes run:
+                               0 = automatic: per instance from a built-in table
+                               keyed by precision, field count, nt and whether the
+                               handle holds one instance or several, chosen by
+                               timing the candidates on MI355X (the same shape
+                               always gets the same schedule; an instance alone
+                               and the same instance in a batch may differ in
+                               rounding);
+                               1 = two passes per z-step (column and row tiles of
+                               a four-step FFT) for every instance;
+                               2 = resident where served: one workgroup holds an
+                               instance for a whole pass and its boundary
+                               (FP32 nt 2^10..2^12, FP64 2^10..2^11; split order
+                               2, one crystal), two passes for the others.
+                               Resident results differ from two-pass ones by
+                               rounding only. Else OPO_EINVAL                     */
     int32_t use_graph;      /* 1 = replay each round trip from a hipGraph
                                (default), -1 = plain launches                     */
     int32_t profile;        /* 1 = bracket every kernel launch with a pair of
@@ -303,10 +319,19 @@ int opo_get_record(opo_t *h, int32_t inst, int32_t field, int32_t rt, double *ou
 /* Time samples t_j [ps] and angular frequencies w_k [rad/ps] of an instance. */
 int opo_get_grid(opo_t *h, int32_t inst, double *t, double *omega);
 
+/* The schedule instance `inst` runs (see opo_options_t.schedule): the four-step
+ * split nt = n1 * n2 of its column and row tiles (log2 of each; the adaptive step
+ * and the spectrum read-out use them for every instance), and whether its
+ * fixed-step passes run resident (1) or as two passes per z-step (0). Any
+ * output pointer may be NULL. OPO_EINVAL for a bad instance. */
+int opo_get_plan(opo_t *h, int32_t inst, int32_t *log2_n1, int32_t *log2_n2, int32_t *resident);
+
 /* Kernel classes timed by the profile option: column pass, row pass, energy
- * reduction, and the mixed pass that runs the column tiles of one half of a
- * batch together with the row tiles of the other half. */
-enum { OPO_K_COLUMN = 0, OPO_K_ROW = 1, OPO_K_ENERGY = 2, OPO_K_MIXED = 3, OPO_K_CLASSES = 4 };
+ * reduction, the mixed pass that runs the column tiles of one half of a batch
+ * together with the row tiles of the other half, and the resident pass (under
+ * the profile option it runs before the two-pass launches instead of beside
+ * them). */
+enum { OPO_K_COLUMN = 0, OPO_K_ROW = 1, OPO_K_ENERGY = 2, OPO_K_MIXED = 3, OPO_K_RESIDENT = 4, OPO_K_CLASSES = 5 };
 
 /* Device time [ms] summed over launches, and launch counts, of each kernel
  * class since the handle was created (profile option), OPO_K_CLASSES

@@ -24,7 +24,7 @@ LIB_SANITIZE = os.path.join(PKG, "libopo_sanitize.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 UNITS = ["opo.hip", "k_common.hip", "k_f32_pass.hip", "k_f64_pass.hip", "k_f32_mixed3.hip",
-         "k_f32_mixed2.hip", "k_f64_mixed.hip"]
+         "k_f32_mixed2.hip", "k_f64_mixed.hip", "k_resident.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

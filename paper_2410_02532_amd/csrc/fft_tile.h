@@ -241,12 +241,13 @@ template <int RAD, int DIR, typename V> __device__ __forceinline__ void dft(V *x
     else dft2<DIR>(x);
 }
 
-// Radix of the stage that follows sub-transforms of length P.
-// Radix 16 serves transforms of up to 2048 points (at 4096 four radix-8
-// stages ran faster than three radix-16 ones).
-template <int N, int PF, int P> __host__ __device__ constexpr int stage_radix()
+// Radix of the stage that follows sub-transforms of length P. Radix 16 serves
+// transforms of up to R16 points: 2048 in the row tiles (at 4096 four radix-8
+// stages ran faster than three radix-16 ones there); the resident passes, whose
+// threads hold 16 samples of a transform anyway, use it at every length.
+template <int N, int PF, int P, int R16 = 2048> __host__ __device__ constexpr int stage_radix()
 {
-    return (N <= 2048 && N / P >= 16 && PF % 16 == 0) ? 16
+    return (N <= R16 && N / P >= 16 && PF % 16 == 0) ? 16
            : (N / P >= 8 && PF % 8 == 0) ? 8
            : (N / P >= 4 && PF % 4 == 0) ? 4
                                           : 2;
@@ -313,26 +314,107 @@ __device__ __forceinline__ void reg_stage(cplx<R> (&v)[NTR][PF], cplx<R> *lds, c
     }
 }
 
-template <typename R, int N, int PF, int NTR, int DIR, int LS, int P>
+template <typename R, int N, int PF, int NTR, int DIR, int LS, int P, int R16>
 __device__ __forceinline__ void reg_fft_from(cplx<R> (&v)[NTR][PF], cplx<R> *lds, const int (&base)[NTR],
                                              int t, const Phasor<R> *__restrict__ tw)
 {
     if constexpr (P < N) {
-        constexpr int RS = stage_radix<N, PF, P>();
+        constexpr int RS = stage_radix<N, PF, P, R16>();
         reg_stage<R, N, PF, NTR, DIR, LS, RS, P>(v, lds, base, t, tw);
-        reg_fft_from<R, N, PF, NTR, DIR, LS, P * RS>(v, lds, base, t, tw);
+        reg_fft_from<R, N, PF, NTR, DIR, LS, P * RS, R16>(v, lds, base, t, tw);
     }
 }
 
 // Unnormalized DFT (DIR -1: e^{-...}, +1: e^{+...}) of NTR transforms of
 // length N. On entry and on exit v[tr][m] is sample t + m*(N/PF). Every
 // thread of the workgroup must call it (it synchronizes the workgroup when
-// N > PF). LS is the LDS element stride between consecutive positions.
-template <typename R, int N, int PF, int NTR, int DIR, int LS>
+// N > PF). LS is the LDS element stride between consecutive positions; radix-16
+// stages serve transforms of up to R16 points.
+template <typename R, int N, int PF, int NTR, int DIR, int LS, int R16 = 2048>
 __device__ __forceinline__ void reg_fft(cplx<R> (&v)[NTR][PF], cplx<R> *lds, const int (&base)[NTR], int t,
                                         const Phasor<R> *__restrict__ tw)
 {
-    reg_fft_from<R, N, PF, NTR, DIR, LS, 1>(v, lds, base, t, tw);
+    reg_fft_from<R, N, PF, NTR, DIR, LS, 1, R16>(v, lds, base, t, tw);
+}
+
+// The same transforms stage by stage through one transform's worth of LDS:
+// each stage loads its twiddles once and then writes, exchanges and reads
+// back the NTR transforms in turn (the arithmetic of each transform is that of
+// reg_fft). Used where NTR transforms would not fit LDS together.
+template <typename R, int N, int PF, int NTR, int DIR, int RS, int P>
+__device__ __forceinline__ void reg_stage_seq(cplx<R> (&v)[NTR][PF], cplx<R> *lds, int t,
+                                              const Phasor<R> *__restrict__ tw)
+{
+    using V = cplx<R>;
+    constexpr int NBT = PF / RS;
+    constexpr int STRIDE = N / PF;
+    constexpr bool LAST = P * RS == N;
+    Phasor<R> w[NBT][RS];
+    if constexpr (P > 1) {
+#pragma unroll
+        for (int u = 0; u < NBT; ++u) {
+            const int k = (t + u * STRIDE) & (P - 1);
+            const Phasor<R> *q = tw + tw_index(RS, P, k);
+#pragma unroll
+            for (int r = 1; r < RS; ++r)
+                w[u][r] = q[r - 1];
+        }
+    }
+#pragma unroll
+    for (int tr = 0; tr < NTR; ++tr) {
+#pragma unroll
+        for (int u = 0; u < NBT; ++u) {
+            V x[RS];
+#pragma unroll
+            for (int r = 0; r < RS; ++r)
+                x[r] = v[tr][u + r * NBT];
+            if constexpr (P > 1) {
+#pragma unroll
+                for (int r = 1; r < RS; ++r)
+                    x[r] = pmul<(DIR > 0)>(x[r], w[u][r]);
+            }
+            dft<RS, DIR>(x);
+            if constexpr (LAST) {
+#pragma unroll
+                for (int r = 0; r < RS; ++r)
+                    v[tr][u + r * NBT] = x[r];
+            } else {
+                const int i = t + u * STRIDE;
+                const int k = i & (P - 1);
+                const int j = (i - k) * RS + k;
+#pragma unroll
+                for (int r = 0; r < RS; ++r)
+                    lds[lds_index<R>(j + r * P)] = x[r];
+            }
+        }
+        if constexpr (!LAST) {
+            lds_sync();
+#pragma unroll
+            for (int m = 0; m < PF; ++m)
+                v[tr][m] = lds[lds_index<R>(t + m * STRIDE)];
+            lds_sync();
+        }
+    }
+}
+
+template <typename R, int N, int PF, int NTR, int DIR, int P, int R16>
+__device__ __forceinline__ void reg_fft_seq_from(cplx<R> (&v)[NTR][PF], cplx<R> *lds, int t,
+                                                 const Phasor<R> *__restrict__ tw)
+{
+    if constexpr (P < N) {
+        constexpr int RS = stage_radix<N, PF, P, R16>();
+        reg_stage_seq<R, N, PF, NTR, DIR, RS, P>(v, lds, t, tw);
+        reg_fft_seq_from<R, N, PF, NTR, DIR, P * RS, R16>(v, lds, t, tw);
+    }
+}
+
+// Unnormalized DFT of NTR transforms of length N, one at a time through LDS
+// positions 0..N-1 (stride 1), in the layout of reg_fft.
+template <typename R, int N, int PF, int NTR, int DIR, int R16 = 2048>
+__device__ __forceinline__ void reg_fft_seq(cplx<R> (&v)[NTR][PF], cplx<R> *lds, int t,
+                                            const Phasor<R> *__restrict__ tw)
+{
+    reg_fft_seq_from<R, N, PF, NTR, DIR, 1, R16>(v, lds, t, tw);
 }
 
 } // namespace opo

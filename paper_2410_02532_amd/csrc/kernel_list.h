@@ -48,6 +48,18 @@
     DECL __global__ void mixed_pass<double, 1, 1, NF>(StepArgs<double>, StepArgs<double>);       \
     DECL __global__ void mixed_pass<double, 2, 1, NF>(StepArgs<double>, StepArgs<double>);
 
+// Resident passes: FP32 nt 2^10..2^12, FP64 2^10..2^11, two or three waves.
+#define OPO_RESIDENT_KERNELS_NF(DECL, NF)                                                         \
+    DECL __global__ void resident_pass<float, 10, NF>(StepArgs<float>);                           \
+    DECL __global__ void resident_pass<float, 11, NF>(StepArgs<float>);                           \
+    DECL __global__ void resident_pass<float, 12, NF>(StepArgs<float>);                           \
+    DECL __global__ void resident_pass<double, 10, NF>(StepArgs<double>);                         \
+    DECL __global__ void resident_pass<double, 11, NF>(StepArgs<double>);
+
+#define OPO_RESIDENT_KERNELS(DECL)                                                                 \
+    OPO_RESIDENT_KERNELS_NF(DECL, 2)                                                               \
+    OPO_RESIDENT_KERNELS_NF(DECL, 3)
+
 #define OPO_ALL_KERNELS(DECL)                                                                      \
     OPO_PASS_KERNELS_F32(DECL)                                                                     \
     OPO_PASS_KERNELS_F64(DECL)                                                                     \
@@ -56,4 +68,5 @@
     OPO_MIXED_KERNELS_F32_CR12(DECL, 2)                                                            \
     OPO_MIXED_KERNELS_F32_CR12(DECL, 3)                                                            \
     OPO_MIXED_KERNELS_F64(DECL, 2)                                                                 \
-    OPO_MIXED_KERNELS_F64(DECL, 3)
+    OPO_MIXED_KERNELS_F64(DECL, 3)                                                                 \
+    OPO_RESIDENT_KERNELS(DECL)

@@ -3,6 +3,7 @@
 // crystal pass and of a cavity round trip, hipGraph replay, read-back.
 #include "opo.h"
 #include "kernel_list.h"
+#include "schedule.h"
 
 #include <algorithm>
 #include <cmath>
@@ -147,6 +148,31 @@ template <typename R, int NF> static const void *mixed_fn_nf(int cr, int rr)
     }
 }
 
+// Resident pass for instances of 2^ln points and nf waves (kResMinLog2..kResMaxLog2).
+template <typename R, int NF> static const void *resident_fn_nf(int ln)
+{
+    switch (ln) {
+    case 10: return reinterpret_cast<const void *>(&resident_pass<R, 10, NF>);
+    case 11: return reinterpret_cast<const void *>(&resident_pass<R, 11, NF>);
+    case 12:
+        if constexpr (kResMaxLog2<R> >= 12) return reinterpret_cast<const void *>(&resident_pass<R, 12, NF>);
+        return nullptr;
+    default: return nullptr;
+    }
+}
+template <typename R> static const void *resident_fn(int ln, int nf)
+{
+    return nf == 2 ? resident_fn_nf<R, 2>(ln) : resident_fn_nf<R, 3>(ln);
+}
+static int resident_threads(int ln, int precision)
+{
+    return (1 << ln) / (precision == OPO_F64 ? res_pf<double, 10>() : res_pf<float, 10>());
+}
+static bool resident_shape(int ln, int precision)
+{
+    return ln >= kResMinLog2 && ln <= (precision == OPO_F64 ? kResMaxLog2<double> : kResMaxLog2<float>);
+}
+
 // Mixed kernel for column range cr of nf-wave instances and row range rr.
 template <typename R> static const void *mixed_fn(int cr, int rr, int nf)
 {
@@ -175,7 +201,18 @@ struct opo_s {
     std::vector<InstDesc> inst;
     InstDesc *d_inst = nullptr;
     int tiles_a = 0, tiles_b = 0;
-    std::vector<Group> groups_a, groups_b;   // tiles of one size range (and half)
+    std::vector<Group> groups_a, groups_b;   // tiles of one size range (and half), two-pass instances
+    // resident instances: their column and row tiles follow those of the two-pass
+    // instances (the adaptive step and the spectrum read-out run them), and
+    // their fixed-step passes run in resident_pass launches, one group per
+    // (log2 nt, nf) over d_res_inst[tile0 .. tile0 + count)
+    std::vector<Group> res_groups_a, res_groups_b, res_launch;
+    int *d_res_inst = nullptr;
+    // the resident launches' branches of a pass or round trip: one stream and join
+    // event per launch group, so the shapes run concurrently
+    std::vector<hipStream_t> sides;
+    std::vector<hipEvent_t> ev_join;
+    hipEvent_t ev_fork = nullptr;
     bool mixed = false;              // two halves a launch apart, mixed launches
     int *d_map[2] = {nullptr, nullptr};  // workgroup -> tile maps of the two mixed launches
     int map_len[2] = {0, 0};
@@ -436,7 +473,12 @@ static void release(opo_t *h)
     if (h->graph) (void)hipGraphExecDestroy(h->graph);
     if (h->a_graph) (void)hipGraphExecDestroy(h->a_graph);
     if (h->own_state && h->state) (void)hipFree(h->state);
-    void *bufs[] = {h->d_w4tab, h->pump, h->d_inst, h->d_tile_a, h->d_tile_b, h->d_tw, h->d_disp, h->d_map[0], h->d_map[1],
+    if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
+    for (hipEvent_t e : h->ev_join)
+        if (e) (void)hipEventDestroy(e);
+    for (hipStream_t st : h->sides)
+        if (st) (void)hipStreamDestroy(st);
+    void *bufs[] = {h->d_res_inst, h->d_w4tab, h->pump, h->d_inst, h->d_tile_a, h->d_tile_b, h->d_tw, h->d_disp, h->d_map[0], h->d_map[1],
                     h->d_partial, h->d_hist, h->d_counter, h->spec_buf, h->d_record, h->d_snap,
                     h->a_uc, h->a_uf, h->a_tab, h->d_actl, h->d_apart};
     for (void *b : bufs)
@@ -546,24 +588,30 @@ template <typename R> static void set_half_steps(const opo_t *h, StepArgs<R> &a,
     a.hf_this = 0.5 * tau;
 }
 
-template <typename R> static hipError_t launch_a(opo_t *h, StepArgs<R> a, int flags, int step, int half = -1)
+// Column launches over the two-pass instances (of one half, or all), and with
+// all_tiles also over the tiles of the resident instances (the adaptive step
+// and the spectrum read-out).
+template <typename R>
+static hipError_t launch_a(opo_t *h, StepArgs<R> a, int flags, int step, int half = -1, bool all_tiles = false)
 {
     a.tile_inst = h->d_tile_a;
     a.flags = flags;
     set_half_steps<R>(h, a, step);
     HIP_RET(prof_begin(h, OPO_K_COLUMN));
-    for (const Group &g : h->groups_a) {
-        if (half >= 0 && g.half != half) continue;
-        a.tile0 = g.tile0;
-        a.tile_count = g.count;
-        void *args[] = {&a};
-        HIP_RET(hipLaunchKernel(column_fn<R>(g.ln, g.nf), dim3(g.count), dim3(kThreads), args, h->lds_a,
-                                h->stream));
-    }
+    for (int set = 0; set < (all_tiles ? 2 : 1); ++set)
+        for (const Group &g : set ? h->res_groups_a : h->groups_a) {
+            if (half >= 0 && g.half != half) continue;
+            a.tile0 = g.tile0;
+            a.tile_count = g.count;
+            void *args[] = {&a};
+            HIP_RET(hipLaunchKernel(column_fn<R>(g.ln, g.nf), dim3(g.count), dim3(kThreads), args, h->lds_a,
+                                    h->stream));
+        }
     return prof_end(h);
 }
 
-template <typename R> static hipError_t launch_b(opo_t *h, StepArgs<R> a, int flags, int step = 0, int sel = -1)
+template <typename R>
+static hipError_t launch_b(opo_t *h, StepArgs<R> a, int flags, int step = 0, int sel = -1, bool all_tiles = false)
 {
     a.tile_inst = h->d_tile_b;
     a.flags = flags;
@@ -571,13 +619,50 @@ template <typename R> static hipError_t launch_b(opo_t *h, StepArgs<R> a, int fl
     substep(h, step, z, tau, a.disp_sel);
     if (sel >= 0) a.disp_sel = sel;
     HIP_RET(prof_begin(h, OPO_K_ROW));
-    for (const Group &g : h->groups_b) {
+    for (int set = 0; set < (all_tiles ? 2 : 1); ++set)
+        for (const Group &g : set ? h->res_groups_b : h->groups_b) {
+            a.tile0 = g.tile0;
+            a.tile_count = g.count;
+            void *args[] = {&a};
+            HIP_RET(hipLaunchKernel(row_fn<R>(g.ln), dim3(g.count), dim3(kThreads), args, h->lds_b, h->stream));
+        }
+    return prof_end(h);
+}
+
+// The resident launches of a pass (flags as in resident_pass): one per shape,
+// each on its own side stream between the fork event and its join event
+// (parallel branches of the captured graph, which the shapes fill side by side),
+// or all on the handle's stream under the profile option.
+template <typename R> static hipError_t launch_resident(opo_t *h, StepArgs<R> a, int flags)
+{
+    if (h->res_launch.empty()) return hipSuccess;
+    if (!h->profile) HIP_RET(hipEventRecord(h->ev_fork, h->stream));
+    a.tile_inst = h->d_res_inst;
+    a.flags = flags;
+    HIP_RET(prof_begin(h, OPO_K_RESIDENT));
+    for (size_t q = 0; q < h->res_launch.size(); ++q) {
+        const Group &g = h->res_launch[q];
+        hipStream_t st = h->profile ? h->stream : h->sides[q];
+        if (!h->profile) HIP_RET(hipStreamWaitEvent(st, h->ev_fork, 0));
         a.tile0 = g.tile0;
         a.tile_count = g.count;
+        const int prec = sizeof(R) == 8 ? OPO_F64 : OPO_F32;
+        const size_t lds = static_cast<size_t>(lds_elems<R>(1 << g.ln)) * sizeof(cplx<R>);
         void *args[] = {&a};
-        HIP_RET(hipLaunchKernel(row_fn<R>(g.ln), dim3(g.count), dim3(kThreads), args, h->lds_b, h->stream));
+        HIP_RET(hipLaunchKernel(resident_fn<R>(g.ln, g.nf), dim3(g.count), dim3(resident_threads(g.ln, prec)), args,
+                                lds, st));
+        if (!h->profile) HIP_RET(hipEventRecord(h->ev_join[q], st));
     }
     return prof_end(h);
+}
+
+// The handle's stream waits for the resident branches (before the energies).
+static hipError_t join_resident(opo_t *h)
+{
+    if (h->res_launch.empty() || h->profile) return hipSuccess;
+    for (hipEvent_t e : h->ev_join)
+        HIP_RET(hipStreamWaitEvent(h->stream, e, 0));
+    return hipSuccess;
 }
 
 // Column tiles of half `ch` (flags, step) with the row tiles (B_DISP) of the
@@ -613,6 +698,7 @@ template <typename R> static hipError_t launch_mixed(opo_t *h, StepArgs<R> a, in
 template <typename R>
 static hipError_t enqueue_pass(opo_t *h, StepArgs<R> a, int nz_steps, int first, int last)
 {
+    if (h->groups_a.empty()) return hipSuccess;           // every instance is resident
     const int nz = nz_steps * (h->order == 4 ? 3 : 1);   // symmetrized steps of the pass
     if (h->mixed) {
         // half 0 runs one launch ahead of half 1
@@ -643,6 +729,11 @@ template <typename R> static hipError_t enqueue_roundtrip(opo_t *h)
     a.snap = static_cast<cplx<R> *>(h->d_snap);
     const int eom = h->any_eom ? A_EOM : 0;
     const int K = h->n_stage;
+    // resident instances (one crystal only): the whole round trip in one launch
+    // per shape, beside the two-pass launches
+    a.inst = h->d_inst;
+    a.nz = h->stage_nz[0];
+    HIP_RET(launch_resident<R>(h, a, A_REFRESH | A_ENERGY | (h->any_gdd ? A_GDD : 0) | A_MIRROR | eom));
     // the crystals in order, each from its own entrance; the boundary after the last
     for (int st = 0; st < K; ++st) {
         a.inst = h->d_inst + static_cast<size_t>(st) * h->n_inst;
@@ -650,7 +741,7 @@ template <typename R> static hipError_t enqueue_roundtrip(opo_t *h)
         const int first = st == 0 ? A_REFRESH : 0;
         if (st + 1 < K) {
             HIP_RET(enqueue_pass<R>(h, a, a.nz, first, 0));
-        } else if (h->any_gdd) {
+        } else if (h->any_gdd && !h->groups_a.empty()) {
             HIP_RET(enqueue_pass<R>(h, a, a.nz, first, A_ENERGY | A_FWD));
             HIP_RET(launch_b<R>(h, a, B_GDD));
             HIP_RET(launch_a<R>(h, a, A_INV | A_MIRROR | eom, 0));
@@ -658,6 +749,7 @@ template <typename R> static hipError_t enqueue_roundtrip(opo_t *h)
             HIP_RET(enqueue_pass<R>(h, a, a.nz, first, A_ENERGY | A_MIRROR | eom));
         }
     }
+    HIP_RET(join_resident(h));
     HIP_RET(prof_begin(h, OPO_K_ENERGY));
     energy_reduce<<<1, kThreads, 0, h->stream>>>(h->d_inst, h->n_inst, h->d_partial, h->d_hist,
                                                  h->d_counter, kHistChunk);
@@ -676,6 +768,17 @@ template <typename R> static int setup_kernels(opo_t *h)
         if (!row_fn<R>(g.ln)) return fail(OPO_EINVAL, "internal: no row kernel for this size");
         HIP_TRY(hipFuncSetAttribute(row_fn<R>(g.ln), hipFuncAttributeMaxDynamicSharedMemorySize,
                                     static_cast<int>(h->lds_b)));
+    }
+    for (const Group &g : h->res_groups_a)
+        HIP_TRY(hipFuncSetAttribute(column_fn<R>(g.ln, g.nf), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(h->lds_a)));
+    for (const Group &g : h->res_groups_b)
+        HIP_TRY(hipFuncSetAttribute(row_fn<R>(g.ln), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(h->lds_b)));
+    for (const Group &g : h->res_launch) {
+        if (!resident_fn<R>(g.ln, g.nf)) return fail(OPO_EINVAL, "internal: no resident kernel for this size");
+        HIP_TRY(hipFuncSetAttribute(resident_fn<R>(g.ln, g.nf), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    static_cast<int>(lds_elems<R>(1 << g.ln) * sizeof(cplx<R>))));
     }
     if (h->mixed)
         for (int hf = 0; hf < 2; ++hf) {
@@ -702,7 +805,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     if (opt.n_crystals < 0) return fail(OPO_EINVAL, "n_crystals must be >= 0");
     if (opt.col_log2 != 0 && (opt.col_log2 < 4 || opt.col_log2 > kMaxLog2N2))
         return fail(OPO_EINVAL, "col_log2 must be 0 or 4.." + std::to_string(kMaxLog2N2));
-    if (opt.reserved0 != 0) return fail(OPO_EINVAL, "reserved option fields must be 0");
+    if (opt.schedule < 0 || opt.schedule > 2) return fail(OPO_EINVAL, "schedule must be 0, 1 or 2");
     if (opt.split_order != 0 && opt.split_order != 2 && opt.split_order != 4)
         return fail(OPO_EINVAL, "split_order must be 2, 4 or 0 (= 2)");
     // the longest symmetrized step of the fourth-order composition is |b| dz
@@ -754,8 +857,15 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     h->inst.resize(n);
     for (int i = 0; i < n; ++i) {
         InstDesc &d = h->inst[i];
-        const Plan p = make_plan(f[i].nt, opt.precision, opt.col_log2);
+        // schedule: the table's entry for this shape (schedule 0), or two-pass
+        // (1) / resident where served (2); an explicit col_log2 sets the split
+        const int l2 = ilog2(f[i].nt);
+        const Schedule sc = opt.schedule == 0 ? schedule_lookup(opt.precision == OPO_F64, nfields(f[i]), l2, n > 1)
+                                              : Schedule{0, opt.schedule == 2 ? 1 : 0};
+        const Plan p = make_plan(f[i].nt, opt.precision, opt.col_log2 != 0 ? opt.col_log2 : sc.col_log2);
         fill_desc(d, f[i], c[i * K], k[i], p);
+        // resident passes: shapes resident_pass serves, second-order steps, one crystal
+        d.resident = sc.resident && resident_shape(l2, opt.precision) && h->order == 2 && K == 1 ? 1 : 0;
         d.off = off;
         off += static_cast<long long>(d.nf) * d.nt;
         if (f[i].pump_in) {
@@ -792,9 +902,10 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     // each half then has one column and one row size range (a GDD row pass
     // and the column pass after it run over both halves at the round-trip end)
     std::vector<int> half(n, 0);
-    if (n >= 2) {
-        std::vector<int> order(n);
-        for (int i = 0; i < n; ++i) order[i] = i;
+    std::vector<int> order;
+    for (int i = 0; i < n; ++i)
+        if (!h->inst[i].resident) order.push_back(i);
+    if (order.size() >= 2) {
         std::stable_sort(order.begin(), order.end(),
                          [&](int x, int y) { return h->inst[x].nt > h->inst[y].nt; });
         long long load[2] = {0, 0};
@@ -813,7 +924,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
                 const int first = h->tiles_a;
                 for (int i = 0; i < n; ++i) {
                     InstDesc &d = h->inst[i];
-                    if (half[i] != hf || d.nf != nf || range_of(kColRanges, d.log2n2) != g) continue;
+                    if (d.resident || half[i] != hf || d.nf != nf || range_of(kColRanges, d.log2n2) != g) continue;
                     d.tile_a0 = h->tiles_a;
                     h->tiles_a += d.tiles_a;
                     tile_a_inst.insert(tile_a_inst.end(), d.tiles_a, i);
@@ -825,12 +936,45 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
             const int first = h->tiles_b;
             for (int i = 0; i < n; ++i) {
                 InstDesc &d = h->inst[i];
-                if (half[i] != hf || range_of(kRowRanges, d.log2n1) != g) continue;
+                if (d.resident || half[i] != hf || range_of(kRowRanges, d.log2n1) != g) continue;
                 d.tile_b0 = h->tiles_b;
                 h->tiles_b += d.tiles_b;
                 tile_b_inst.insert(tile_b_inst.end(), d.tiles_b, i);
             }
             if (h->tiles_b > first) h->groups_b.push_back({g, first, h->tiles_b - first, hf, 0});
+        }
+    // the resident instances' tiles follow, and their launch groups by (log2 nt, nf)
+    std::vector<int> res_inst;
+    for (int nf = 3; nf >= 2; --nf)
+        for (int g = 0; g < ncr; ++g) {
+            const int first = h->tiles_a;
+            for (int i = 0; i < n; ++i) {
+                InstDesc &d = h->inst[i];
+                if (!d.resident || d.nf != nf || range_of(kColRanges, d.log2n2) != g) continue;
+                d.tile_a0 = h->tiles_a;
+                h->tiles_a += d.tiles_a;
+                tile_a_inst.insert(tile_a_inst.end(), d.tiles_a, i);
+            }
+            if (h->tiles_a > first) h->res_groups_a.push_back({g, first, h->tiles_a - first, 0, nf});
+        }
+    for (int g = 0; g < nrr; ++g) {
+        const int first = h->tiles_b;
+        for (int i = 0; i < n; ++i) {
+            InstDesc &d = h->inst[i];
+            if (!d.resident || range_of(kRowRanges, d.log2n1) != g) continue;
+            d.tile_b0 = h->tiles_b;
+            h->tiles_b += d.tiles_b;
+            tile_b_inst.insert(tile_b_inst.end(), d.tiles_b, i);
+        }
+        if (h->tiles_b > first) h->res_groups_b.push_back({g, first, h->tiles_b - first, 0, 0});
+    }
+    for (int ln = kResMaxLog2<float>; ln >= kResMinLog2; --ln)
+        for (int nf = 3; nf >= 2; --nf) {
+            const int first = static_cast<int>(res_inst.size());
+            for (int i = 0; i < n; ++i)
+                if (h->inst[i].resident && h->inst[i].nf == nf && h->inst[i].log2nt == ln) res_inst.push_back(i);
+            const int cnt = static_cast<int>(res_inst.size()) - first;
+            if (cnt > 0) h->res_launch.push_back({ln, first, cnt, 0, nf});
         }
     if (static_cast<int>(tile_a_inst.size()) != h->tiles_a || static_cast<int>(tile_b_inst.size()) != h->tiles_b)
         return bail(fail(OPO_EINVAL, "internal: a transform length has no kernel"));
@@ -897,7 +1041,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         int same = -1;
         for (int o : h->disp_owner) {
             const InstDesc &e = h->inst[o];
-            if (e.nt == d.nt && e.nf == d.nf && e.length_mm == d.length_mm &&
+            if (e.nt == d.nt && e.nf == d.nf && e.resident == d.resident && e.length_mm == d.length_mm &&
                 h->stage_nz[o / n] == h->stage_nz[q / n] &&
                 std::memcmp(e.disp, d.disp, sizeof(d.disp)) == 0 &&
                 std::memcmp(e.alpha_half, d.alpha_half, sizeof(d.alpha_half)) == 0) {
@@ -952,6 +1096,19 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
                       hipMalloc(reinterpret_cast<void **>(&h->d_map[1]), maps[1].size() * sizeof(int)) != hipSuccess)))
         return bail(fail(OPO_ENOMEM, "hipMalloc of the tables failed"));
 
+    if (!res_inst.empty()) {
+        if (hipMalloc(reinterpret_cast<void **>(&h->d_res_inst), res_inst.size() * sizeof(int)) != hipSuccess)
+            return bail(fail(OPO_ENOMEM, "hipMalloc of the resident instance list failed"));
+        if (hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(OPO_EDEVICE, "creating the resident branches' fork event failed"));
+        h->sides.assign(h->res_launch.size(), nullptr);
+        h->ev_join.assign(h->res_launch.size(), nullptr);
+        for (size_t q = 0; q < h->res_launch.size(); ++q)
+            if (hipStreamCreateWithFlags(&h->sides[q], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&h->ev_join[q], hipEventDisableTiming) != hipSuccess)
+                return bail(fail(OPO_EDEVICE, "creating the resident branches' streams and events failed"));
+    }
+
     h->lds_a = (opt.precision == OPO_F64 ? lds_elems<double>(static_cast<int>(max_a))
                                          : lds_elems<float>(static_cast<int>(max_a))) * es;
     h->lds_b = (opt.precision == OPO_F64 ? lds_elems<double>(static_cast<int>(max_b))
@@ -976,6 +1133,8 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         hipMemcpyAsync(h->d_tile_b, tile_b_inst.data(), tile_b_inst.size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess ||
         (h->mixed && hipMemcpyAsync(h->d_map[0], maps[0].data(), maps[0].size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess) ||
         (h->mixed && hipMemcpyAsync(h->d_map[1], maps[1].data(), maps[1].size() * sizeof(int), hipMemcpyHostToDevice, st) != hipSuccess) ||
+        (!res_inst.empty() && hipMemcpyAsync(h->d_res_inst, res_inst.data(), res_inst.size() * sizeof(int),
+                                             hipMemcpyHostToDevice, st) != hipSuccess) ||
         hipStreamSynchronize(st) != hipSuccess)
         return bail(fail(OPO_EDEVICE, "upload of the instance tables failed"));
     if ((opt.precision == OPO_F64 ? upload_phasors<double>(h->d_tw, twre, twim, st)
@@ -1083,7 +1242,13 @@ template <typename R> static int propagate_impl(opo_t *h, int nz, double dz)
     StepArgs<R> a = base_args<R>(h, h->state);
     a.dz_arg = dz;
     a.zbase = h->z;
+    {
+        StepArgs<R> ar = a;
+        ar.nz = nz;
+        HIP_TRY(launch_resident<R>(h, ar, 0));
+    }
     HIP_TRY(enqueue_pass<R>(h, a, nz, 0, 0));
+    HIP_TRY(join_resident(h));
     h->z += nz * dz;
     const size_t used = h->ev_used;
     h->ev_used = 0;
@@ -1113,19 +1278,19 @@ template <typename R> static hipError_t enqueue_attempt(opo_t *h)
     a.state = uc;                 // one step of dz, from u
     a.adapt_scale = 1.0;
     a.src = u;
-    HIP_RET(launch_a<R>(h, a, A_RK_THIS | A_FWD, 0));
+    HIP_RET(launch_a<R>(h, a, A_RK_THIS | A_FWD, 0, -1, true));
     a.src = nullptr;
-    HIP_RET(launch_b<R>(h, a, B_DISP, 0, 0));
-    HIP_RET(launch_a<R>(h, a, A_INV | A_RK_PREV, 1));
+    HIP_RET(launch_b<R>(h, a, B_DISP, 0, 0, true));
+    HIP_RET(launch_a<R>(h, a, A_INV | A_RK_PREV, 1, -1, true));
     a.state = uf;                 // two steps of dz/2, from u
     a.adapt_scale = 0.5;
     a.src = u;
-    HIP_RET(launch_a<R>(h, a, A_RK_THIS | A_FWD, 0));
+    HIP_RET(launch_a<R>(h, a, A_RK_THIS | A_FWD, 0, -1, true));
     a.src = nullptr;
-    HIP_RET(launch_b<R>(h, a, B_DISP, 0, 0));
-    HIP_RET(launch_a<R>(h, a, A_INV | A_RK_PREV | A_RK_THIS | A_FWD, 1));
-    HIP_RET(launch_b<R>(h, a, B_DISP, 1, 0));
-    HIP_RET(launch_a<R>(h, a, A_INV | A_RK_PREV, 2));
+    HIP_RET(launch_b<R>(h, a, B_DISP, 0, 0, true));
+    HIP_RET(launch_a<R>(h, a, A_INV | A_RK_PREV | A_RK_THIS | A_FWD, 1, -1, true));
+    HIP_RET(launch_b<R>(h, a, B_DISP, 1, 0, true));
+    HIP_RET(launch_a<R>(h, a, A_INV | A_RK_PREV, 2, -1, true));
     adapt_error<R><<<blocks, kThreads, 0, h->stream>>>(h->d_inst, h->d_actl, h->a_chunks, uc, uf, h->d_apart);
     HIP_RET(hipGetLastError());
     adapt_control<<<(h->n_inst + kThreads / 64 - 1) / (kThreads / 64), kThreads, 0, h->stream>>>(
@@ -1317,8 +1482,8 @@ template <typename R> static int spectrum_impl(opo_t *h, int inst, int field, do
     }
     HIP_TRY(hipMemcpyAsync(h->spec_buf, h->state, h->state_bytes, hipMemcpyDeviceToDevice, h->stream));
     StepArgs<R> a = base_args<R>(h, h->spec_buf);
-    HIP_TRY(launch_a<R>(h, a, A_FWD, 0));
-    HIP_TRY(launch_b<R>(h, a, B_FWD_ONLY));
+    HIP_TRY(launch_a<R>(h, a, A_FWD, 0, -1, true));
+    HIP_TRY(launch_b<R>(h, a, B_FWD_ONLY, 0, -1, true));
     std::vector<double> tmp(2 * static_cast<size_t>(d.nt));
     const char *src = static_cast<const char *>(h->spec_buf) + (d.off + static_cast<long long>(field) * d.nt) * h->elem;
     HIP_TRY(state_to_host<R>(tmp.data(), src, d.nt, h->stream));
@@ -1658,6 +1823,18 @@ int opo_get_grid(opo_t *h, int32_t inst, double *t, double *omega)
         if (t) t[j] = -0.5 * T + j * (T / nt);
         if (omega) omega[j] = kTwoPi * (j < nt / 2 ? j : j - nt) / T;
     }
+    return OPO_OK;
+}
+
+int opo_get_plan(opo_t *h, int32_t inst, int32_t *log2_n1, int32_t *log2_n2, int32_t *resident)
+{
+    int rc = check(h);
+    if (rc) return rc;
+    if (inst < 0 || inst >= h->n_inst) return fail(OPO_EINVAL, "bad instance");
+    const InstDesc &d = h->inst[inst];
+    if (log2_n1) *log2_n1 = d.log2n1;
+    if (log2_n2) *log2_n2 = d.log2n2;
+    if (resident) *resident = d.resident;
     return OPO_OK;
 }
 

@@ -1,0 +1,39 @@
+// schedule.h -- the automatic schedule of an instance, by shape: the four-step
+// split (log2 of the column length, 0 = the default split of make_plan) and
+// whether fixed-step passes run resident (one workgroup holds the instance).
+// The entries are chosen by timing the candidate schedules on the device
+// (paper_2410_02532_amd/tune.py, which writes schedule_table.inc); the lookup
+// itself is a plain table, so one shape always gets one schedule and results
+// do not depend on timings taken at run time. An instance is "alone" when its
+// handle holds no other; the schedules differ because an instance alone is
+// bound by the serial time of one tile, a batch by throughput.
+#pragma once
+
+namespace opo {
+
+struct Schedule {
+    int col_log2;   // 0 = default split
+    int resident;   // 1 = resident passes (shapes resident_pass serves only)
+};
+
+struct ScheduleEntry {
+    int f64;        // precision: 0 FP32, 1 FP64
+    int nf;         // coupled waves
+    int log2nt;
+    int batched;    // 0 alone, 1 in a batch
+    Schedule s;
+};
+
+static const ScheduleEntry kScheduleTable[] = {
+#include "schedule_table.inc"
+};
+
+inline Schedule schedule_lookup(bool f64, int nf, int log2nt, bool batched)
+{
+    for (const ScheduleEntry &e : kScheduleTable)
+        if (e.f64 == (f64 ? 1 : 0) && e.nf == nf && e.log2nt == log2nt && e.batched == (batched ? 1 : 0))
+            return e.s;
+    return Schedule{0, 0};
+}
+
+} // namespace opo

@@ -51,6 +51,8 @@ struct InstDesc {
     int nf;               // coupled waves: 3 (p, s, i) or 2 (p, s; degenerate)
     int pump_windows;     // > 1: round trip m reads window m of the input pump (zero after)
     int kerr;             // Kerr term on (gamma below)
+    int resident;         // fixed-step passes run in resident_pass (one workgroup holds
+                          // the instance); its propagator table is then in natural bin order
     double length_mm;
     double kappa[3];      // 1/mm per V/m; two waves: (kappa_p2, kappa_s, 0)
     double dk_rev;        // dk / (2 pi)  [rev/mm]
@@ -75,6 +77,7 @@ enum : int {
                       // (also: record the fields leaving the crystal with A_ENERGY)
     A_RK_THIS = 64,   // first half-step of this z-step
     A_FWD = 128,      // end with the forward column FFT + twiddle (else store samples)
+    A_GDD = 256,      // resident passes: GDD between the energies and the mirror
 };
 
 enum : int {
@@ -790,16 +793,234 @@ __global__ __launch_bounds__(kThreads, (mixed_min_blocks<R, CR, RR>())) void mix
 }
 
 // ------------------------------------------------------------------------
+// Resident pass: one workgroup holds one instance of nt = 2^LN points for a
+// whole crystal pass, and in a round trip also the boundary on both sides, so
+// the fields cross HBM once per pass instead of twice per z-step. Thread t
+// keeps samples t + m*T (m < 16, T = nt/16) of every field in registers: the
+// RK4 half-steps find the NF fields of a time point in one thread, and the
+// full-length transforms of one field at a time (radix-16 Stockham stages with
+// LDS exchanges, fft_tile.h) return the bins in natural order to the same
+// positions, where the natural-order propagator table H_x(k)/nt applies.
+// Shapes: FP32 nt 2^10..2^12 with 16 samples of each field per thread
+// (radix-16 stages), FP64 2^10..2^11 with 8 (radix 8), on nt/PF threads: the
+// registers of one wave per SIMD then hold the fields, a stage's twiddles and
+// the RK4 without spills. (FP32 2^13 spilled with 512 threads of 16 samples
+// and with 1024 of 8; FP64 with 16 samples.)
+constexpr int kResMinLog2 = 10;
+template <typename R> constexpr int kResMaxLog2 = sizeof(R) == 4 ? 12 : 11;
+template <typename R, int LN> __host__ __device__ constexpr int res_pf() { return sizeof(R) == 4 ? 16 : 8; }
+template <typename R, int LN> __host__ __device__ constexpr int res_threads() { return (1 << LN) / res_pf<R, LN>(); }
+
+// Fixed-order sum of three doubles over the W waves of a workgroup; the result
+// is valid in thread 0.
+template <int W> __device__ __forceinline__ void block_sum3_w(double v[3], double *scratch /* [3*W] */)
+{
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        double s = v[x];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            s += __shfl_down(s, o, 64);
+        v[x] = s;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+        for (int x = 0; x < 3; ++x)
+            scratch[x * W + wave] = v[x];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int x = 0; x < 3; ++x) {
+            double s = 0.0;
+            for (int w = 0; w < W; ++w)
+                s += scratch[x * W + w];
+            v[x] = s;
+        }
+}
+
+// The workgroups of a launch run the instances a.tile_inst[a.tile0 + b]. The
+// flags select, as in the column tile: A_REFRESH (snapshot, input pump, zero
+// non-resonant fields) before the pass; A_ENERGY (FP64 energies into the
+// instance's first column-tile partial slot, the others zeroed, and the
+// record), A_GDD, A_MIRROR and A_EOM after it. Without them the launch is a
+// plain pass of nz steps from zbase (explicit dz_arg) or from 0 (L/nz).
+// The table pointer, hidden from the optimizer: loads through it stay in the
+// z-step loop instead of being hoisted out of it and held in registers for the
+// whole pass (the tables are the same at every step).
+template <typename P> __device__ __forceinline__ P *step_local(P *p)
+{
+    asm volatile("" : "+v"(p));
+    return p;
+}
+
+template <typename R, int LN, int NF>
+__global__ __launch_bounds__((res_threads<R, LN>())) void resident_pass(StepArgs<R> a)
+{
+    using V = cplx<R>;
+    constexpr int N = 1 << LN, PF = res_pf<R, LN>(), T = N / PF, W = T / 64;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ Coupling<R> cpl;
+    __shared__ double red[3 * W];
+    V *s = reinterpret_cast<V *>(lds_raw);
+    const int ii = a.tile_inst[a.tile0 + blockIdx.x];
+    const InstDesc &d = a.inst[ii];
+    const int t = threadIdx.x;
+    const int flags = a.flags;
+    const bool stopped = a.counter[2] != 0;   // see column_tile
+    V *g = a.state + d.off + t;
+
+    V v[NF][PF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int m = 0; m < PF; ++m)
+            v[f][m] = g[f * N + m * T];
+
+    const int rt = (flags & (A_REFRESH | A_ENERGY)) ? a.counter[1] : 0;
+    if (flags & A_REFRESH) {
+        if (a.snap != nullptr && !stopped) {
+            V *sp = a.snap + d.off + t;
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int m = 0; m < PF; ++m)
+                    sp[f * N + m * T] = v[f][m];
+        }
+        long long pwin = 0;
+        if (d.pump_windows > 1) pwin = rt < d.pump_windows ? static_cast<long long>(rt) * N : -1;
+        const V pcw = mk<V>(static_cast<R>(d.pump_cw[0]), static_cast<R>(d.pump_cw[1]));
+#pragma unroll
+        for (int m = 0; m < PF; ++m) {
+            V pin = pcw;
+            if (d.pump_off >= 0) pin = pwin >= 0 ? a.pump[d.pump_off + pwin + t + m * T] : mk<V>(R(0), R(0));
+            if (!(d.res_mask & 1)) v[0][m] = pin;
+            else if (d.inject != 0.0) v[0][m] = cadd(v[0][m], pmul(pin, make_phasor<R>(d.inject, 0.0)));
+            if (!(d.res_mask & 2)) v[1][m] = mk<V>(R(0), R(0));
+            if (NF == 3 && !(d.res_mask & 4)) v[NF - 1][m] = mk<V>(R(0), R(0));
+        }
+    }
+
+    const double dz = a.dz_arg > 0.0 ? a.dz_arg : d.length_mm / a.nz;
+    const double zb = a.dz_arg > 0.0 ? a.zbase : 0.0;
+    const bool imag = d.dk_rev == 0.0;   // couplings without a phase: the same at every step
+    const bool kerr = d.kerr != 0;
+    const Phasor<R> *H = a.disp + d.disp_off + t;
+    for (int j = 0; j < a.nz; ++j) {
+        // couplings of step j: [1] its first half from z_j, [0] its second half from z_j + dz/2
+        if (j == 0 || !imag) {
+            __syncthreads();                 // the previous step's readers are done
+            coupling_tile<R>(d, zb + (static_cast<double>(j) + 0.5) * dz, 0.5 * dz,
+                             zb + static_cast<double>(j) * dz, 0.5 * dz, &cpl);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int m = 0; m < PF; ++m)
+            rk4_fields<R, NF>(cpl, 1, imag, kerr, v[0][m], v[1][m], v[NF - 1][m]);
+        reg_fft_seq<R, N, PF, NF, -1, N>(v, s, t, step_local(a.tw));
+        const Phasor<R> *Hj = step_local(H);
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int m = 0; m < PF; ++m) v[f][m] = pmul(v[f][m], Hj[f * N + m * T]);
+        reg_fft_seq<R, N, PF, NF, +1, N>(v, s, t, step_local(a.tw));
+#pragma unroll
+        for (int m = 0; m < PF; ++m)
+            rk4_fields<R, NF>(cpl, 0, imag, kerr, v[0][m], v[1][m], v[NF - 1][m]);
+    }
+
+    if (flags & A_ENERGY) {
+        double en[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int m = 0; m < PF; ++m)
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                en[f] += static_cast<double>(v[f][m].x) * v[f][m].x + static_cast<double>(v[f][m].y) * v[f][m].y;
+        if (a.record != nullptr && rt < a.record_cap && !stopped) {
+            V *rg = a.record + static_cast<long long>(rt) * a.record_stride + d.off + t;
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int m = 0; m < PF; ++m)
+                    rg[f * N + m * T] = v[f][m];
+        }
+        block_sum3_w<W>(en, red);
+        // the instance's column-tile slots of the partial sums (energy_reduce adds them)
+        if (!stopped)
+            for (int q = t; q < d.tiles_a; q += T)
+                for (int x = 0; x < 3; ++x)
+                    a.partial[(d.tile_a0 + q) * 3 + x] = q == 0 ? en[x] : 0.0;
+    }
+    if ((flags & A_GDD) && d.gdd_mask) {
+        const double inv_nt = 1.0 / N;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (!((d.gdd_mask >> f) & 1)) continue;
+            V w[1][PF];
+#pragma unroll
+            for (int m = 0; m < PF; ++m) w[0][m] = v[f][m];
+            reg_fft_seq<R, N, PF, 1, -1, N>(w, s, t, a.tw);
+#pragma unroll
+            for (int m = 0; m < PF; ++m) {
+                const int k = t + m * T;
+                const double ks = static_cast<double>(k < (N >> 1) ? k : k - N);
+                const double2 e = unit_rev(d.gdd_rev * ks * ks);
+                w[0][m] = pmul(w[0][m], make_phasor<R>(e.x * inv_nt, e.y * inv_nt));
+            }
+            reg_fft_seq<R, N, PF, 1, +1, N>(w, s, t, a.tw);
+#pragma unroll
+            for (int m = 0; m < PF; ++m) v[f][m] = w[0][m];
+        }
+    }
+    bool nonfinite = false;
+    if (flags & (A_MIRROR | A_EOM)) {
+#pragma unroll
+        for (int m = 0; m < PF; ++m) {
+            V y0 = v[0][m], y1 = v[1][m], y2 = v[NF - 1][m];
+            if (flags & A_MIRROR) {
+                if (d.res_mask & 1) y0 = pmul(y0, make_phasor<R>(d.mirror[0][0], d.mirror[0][1]));
+                if (d.res_mask & 2) y1 = pmul(y1, make_phasor<R>(d.mirror[1][0], d.mirror[1][1]));
+                if (NF == 3 && (d.res_mask & 4)) y2 = pmul(y2, make_phasor<R>(d.mirror[2][0], d.mirror[2][1]));
+            }
+            if ((flags & A_EOM) && d.eom_mask) {
+                const long long j = t + m * T;
+                const double th = d.eom_beta * unit_rev(d.eom_rev0 + d.eom_rev_step * static_cast<double>(j)).y;
+                double sn, cs;
+                sincos(th, &sn, &cs);
+                const Phasor<R> e = make_phasor<R>(cs, sn);
+                if (d.eom_mask & 1) y0 = pmul(y0, e);
+                if (d.eom_mask & 2) y1 = pmul(y1, e);
+                if (NF == 3 && (d.eom_mask & 4)) y2 = pmul(y2, e);
+            }
+            if (flags & A_MIRROR)
+                nonfinite = nonfinite || !(isfinite(y0.x) && isfinite(y0.y) && isfinite(y1.x) && isfinite(y1.y) &&
+                                           isfinite(y2.x) && isfinite(y2.y));
+            v[0][m] = y0;
+            v[1][m] = y1;
+            if constexpr (NF == 3) v[2][m] = y2;
+        }
+    }
+    if (nonfinite && !stopped) a.counter[3] = 1;   // see column_tile
+    if (!stopped) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int m = 0; m < PF; ++m)
+                g[f * N + m * T] = v[f][m];
+    }
+}
+
+// ------------------------------------------------------------------------
 // Linear propagator of one z-step (Eq. 5) for the nf fields of an instance,
 // H_x(k)/nt = exp{[-alpha_x/2 + i(-db1 w + b2 w^2/2 - b3 w^3/6)] dz}/nt,
 // formed in FP64 (phase reduced modulo one revolution) and stored in the
-// row-pass order: position k2*n1 + k1 holds bin k = k2 + n2*k1.
-template <typename R> __device__ __forceinline__ Phasor<R> propagator(const InstDesc &d, long long q, double dz)
+// row-pass order (position k2*n1 + k1 holds bin k = k2 + n2*k1), or in natural
+// bin order for the resident passes.
+template <typename R>
+__device__ __forceinline__ Phasor<R> propagator(const InstDesc &d, long long q, double dz, bool natural)
 {
     const int f = static_cast<int>(q / d.nt);
     const int p = static_cast<int>(q - static_cast<long long>(f) * d.nt);
     const int k2 = p >> d.log2n1, k1 = p & (d.n1 - 1);
-    const int k = k2 + d.n2 * k1;
+    const int k = natural ? p : k2 + d.n2 * k1;
     const double ks = static_cast<double>(k < (d.nt >> 1) ? k : k - d.nt);
     const double rho = dz * ks * (d.disp[f][0] + ks * (d.disp[f][1] + ks * d.disp[f][2]));
     const double amp = exp(-d.alpha_half[f] * dz) / d.nt;
@@ -816,7 +1037,7 @@ __global__ __launch_bounds__(kThreads) void disp_table(const InstDesc *inst, int
     const long long n = static_cast<long long>(d.nf) * d.nt;
     for (long long q = blockIdx.x * static_cast<long long>(kThreads) + threadIdx.x; q < n;
          q += static_cast<long long>(gridDim.x) * kThreads)
-        out[d.disp_off + q] = propagator<R>(d, q, dz);
+        out[d.disp_off + q] = propagator<R>(d, q, dz, d.resident != 0);
 }
 
 // ------------------------------------------------------------------------
@@ -854,7 +1075,7 @@ __global__ __launch_bounds__(kThreads) void adapt_begin(const InstDesc *inst, co
             const V f = uf[j], c = uc[j];
             u[j] = mk<V>((R(4) * f.x - c.x) / R(3), (R(4) * f.y - c.y) / R(3));
         }
-        if (run) tab[j] = propagator<R>(d, q, 0.5 * st.dz);
+        if (run) tab[j] = propagator<R>(d, q, 0.5 * st.dz, false);   // the adaptive step runs column/row tiles
     }
 }
 

@@ -24,8 +24,9 @@ EXPORTS = ("opo_state_bytes", "opo_init", "opo_init_batch", "ssfm_propagate", "s
            "opo_get_energy_history",
            "opo_get_power_history",
            "opo_get_record", "opo_get_grid", "opo_kernel_times", "opo_info", "opo_destroy",
-           "opo_last_error", "opo_get_spectrum_noalloc")
-KERNEL_CLASSES = ("column_pass", "row_pass", "energy_reduce", "mixed_pass")
+           "opo_last_error", "opo_get_spectrum_noalloc", "opo_get_plan")
+KERNEL_CLASSES = ("column_pass", "row_pass", "energy_reduce", "mixed_pass", "resident_pass")
+SCHEDULES = {"auto": 0, "two_pass": 1, "resident": 2}
 
 _d3 = ctypes.c_double * 3
 _i3 = ctypes.c_int32 * 3
@@ -56,7 +57,7 @@ class OptionsT(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("device", ctypes.c_int32),
                 ("stream", ctypes.c_void_p), ("state", ctypes.c_void_p),
                 ("state_bytes", ctypes.c_uint64), ("col_log2", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("schedule", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("record_rt", ctypes.c_int32),
                 ("n_crystals", ctypes.c_int32), ("split_order", ctypes.c_int32)]
 
@@ -93,6 +94,7 @@ def load():
     lib.opo_get_fields.argtypes = [P, I, I, I, P]
     lib.opo_set_fields.argtypes = [P, I, I, P]
     lib.opo_get_spectrum_noalloc.argtypes = [P, I, P]
+    lib.opo_get_plan.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]
     lib.opo_get_progress.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(D)]
     lib.opo_set_progress.argtypes = [P, I, D, P]
     lib.opo_get_energy_history.argtypes = [P, I, P, I, ctypes.POINTER(I)]
@@ -106,7 +108,7 @@ def load():
     lib.opo_last_error.restype = ctypes.c_char_p
     for name in ("opo_init", "opo_init_batch", "ssfm_propagate", "ssfm_propagate_adaptive",
                  "cavity_roundtrip", "opo_sync",
-                 "opo_get_fields", "opo_set_fields", "opo_get_spectrum_noalloc",
+                 "opo_get_fields", "opo_set_fields", "opo_get_spectrum_noalloc", "opo_get_plan",
                  "opo_get_progress", "opo_set_progress",
                  "opo_get_energy_history", "opo_get_record",
                  "opo_get_power_history",
@@ -203,12 +205,14 @@ class Opo:
     record_rt > 0 keeps the fields leaving the crystal for the first record_rt round trips
     (read with record()). Several crystals per round trip: each instance carries
     "crystals" (in order) and nz is a list of step counts, one per crystal.
+    schedule: "auto" (the library's table by shape), "two_pass" or "resident" (see
+    opo_options_t.schedule in include/opo.h).
     The field state lives in a torch uint8 tensor on ``device``; the library
     runs on a torch stream (default priority) created for the handle.
     """
 
     def __init__(self, instances, nz, precision="f32", device=0, col_log2=0,
-                 use_graph=True, profile=False, record_rt=0, split_order=2):
+                 use_graph=True, profile=False, record_rt=0, split_order=2, schedule="auto"):
         import torch
         lib = load()
         self._lib = lib
@@ -225,7 +229,7 @@ class Opo:
         opt = OptionsT(precision=self.precision, device=device,
                        stream=ctypes.c_void_p(self._stream.cuda_stream),
                        state=ctypes.c_void_p(self._state.data_ptr()), state_bytes=nbytes,
-                       col_log2=int(col_log2), use_graph=1 if use_graph else -1,
+                       col_log2=int(col_log2), schedule=SCHEDULES[schedule], use_graph=1 if use_graph else -1,
                        profile=1 if profile else 0, record_rt=int(record_rt),
                        n_crystals=len(nz) if np.ndim(nz) else 1, split_order=int(split_order))
         h = ctypes.c_void_p()
@@ -283,6 +287,13 @@ class Opo:
         if out.dtype != want or out.numel() != nf * nt or not out.is_contiguous() or out.device != self._dev:
             raise ValueError("out must be a contiguous %s tensor of %d values on %s" % (want, nf * nt, self._dev))
         _check(self._lib.opo_get_spectrum_noalloc(self.h, int(inst), ctypes.c_void_p(out.data_ptr())))
+
+    def plan(self, inst=0):
+        """(log2 n1, log2 n2, resident) of an instance: its four-step split and whether its
+        fixed-step passes run resident."""
+        l1, l2, res = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(self._lib.opo_get_plan(self.h, int(inst), ctypes.byref(l1), ctypes.byref(l2), ctypes.byref(res)))
+        return l1.value, l2.value, bool(res.value)
 
     def progress(self):
         """(round trips completed since opo_init, z of the next ssfm_propagate)."""

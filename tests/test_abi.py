@@ -147,3 +147,32 @@ def test_empty_batch_is_rejected():
     rc, h = _init(f, c, k, n=0)
     assert rc == B.OPO_EINVAL and h.value is None
     assert B.load().opo_state_bytes(0, f, 0) == 0
+
+
+@pytest.mark.parametrize("schedule", [-1, 3])
+def test_bad_schedule_is_rejected(schedule):
+    """The schedule option takes 0 (automatic), 1 (two passes) or 2 (resident where served);
+    checked before any device call."""
+    n, f, c, k, keep = _one()
+    h = ctypes.c_void_p()
+    opt = B.OptionsT(schedule=schedule)
+    assert B.load().opo_init_batch(ctypes.byref(h), 1, f, c, k, ctypes.byref(opt)) == B.OPO_EINVAL
+    assert h.value is None and "schedule" in B.last_error()
+
+
+def test_schedule_table_is_well_formed():
+    """Every entry of the automatic schedule's table names a valid split and asks for the
+    resident pass only where the kernel serves the shape (FP32 2^10..2^12, FP64 2^10..2^11)
+    and only for batches; no key appears twice."""
+    path = os.path.join(ROOT, "paper_2410_02532_amd", "csrc", "schedule_table.inc")
+    rows = [tuple(int(v) for v in re.findall(r"-?\d+", line))
+            for line in open(path) if line.strip().startswith("{")]
+    assert rows
+    keys = [r[:4] for r in rows]
+    assert len(keys) == len(set(keys))
+    for f64, nf, l, batched, col, res in rows:
+        assert f64 in (0, 1) and nf in (2, 3) and batched in (0, 1)
+        assert 1 <= l <= (19 if f64 else 20)
+        assert col == 0 or 4 <= col <= 8
+        if res:
+            assert batched == 1 and 10 <= l <= (11 if f64 else 12), (f64, nf, l)

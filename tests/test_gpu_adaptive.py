@@ -80,12 +80,12 @@ def test_adaptive_batch_uneven():
     insts = [_inst(1024, 3), _inst(8192, 5, deff=25.0, dk=-0.5), _inst(2048, 7, nf=2),
              _inst(4096, 9, n2=2e-17, scale=3.0), _inst(512, 11, deff=0.0)]
     L, tol, dz0 = 2.0, 1e-6, 0.1
-    with B.Opo(insts, 40, precision="f64") as hb:
+    with B.Opo(insts, 40, precision="f64", schedule="two_pass") as hb:
         acc_b, rej_b, z_b = hb.ssfm_propagate_adaptive(L, tol, dz0)
         batch = [hb.get_fields(i) for i in range(len(insts))]
     assert len(set(acc_b.tolist())) > 2                 # the sequences differ
     for i, ins in enumerate(insts):
-        with B.Opo([ins], 40, precision="f64") as h:
+        with B.Opo([ins], 40, precision="f64", schedule="two_pass") as h:
             a1, r1, _ = h.ssfm_propagate_adaptive(L, tol, dz0)
             assert (a1[0], r1[0]) == (acc_b[i], rej_b[i])
             assert np.array_equal(h.get_fields(), batch[i])

@@ -76,13 +76,13 @@ def test_record_capacity_and_batch():
     say("record capacity, batch")
     nt, nz, windows = 1024, 8, 6
     insts = [_windowed(nt, windows, seed=s) for s in (31, 32)]
-    with B.Opo(insts, nz, precision="f32", record_rt=5) as hb:
+    with B.Opo(insts, nz, precision="f32", record_rt=5, schedule="two_pass") as hb:
         hb.cavity_roundtrip(8)
         recs = [[hb.record(m, i) for m in range(5)] for i in range(2)]
         with pytest.raises(B.OpoError):
             hb.record(5, 0)
     for i, ins in enumerate(insts):
-        with B.Opo([ins], nz, precision="f32", record_rt=5) as h:
+        with B.Opo([ins], nz, precision="f32", record_rt=5, schedule="two_pass") as h:
             h.cavity_roundtrip(8)
             for m in range(5):
                 assert np.array_equal(recs[i][m], h.record(m))

@@ -58,11 +58,11 @@ def test_fourth_order_round_trips_batch():
     say("order-4 batch")
     insts = [_case(nt, 30 + b) for b, nt in enumerate([4096, 8192, 4096, 8192])]
     nz, nrt = 8, 3
-    with B.Opo(insts, nz, precision="f32", split_order=4) as hb:
+    with B.Opo(insts, nz, precision="f32", split_order=4, schedule="two_pass") as hb:
         hb.cavity_roundtrip(nrt)
         batch = [(hb.get_fields(i), hb.energy_history(i)) for i in range(len(insts))]
     for i, ins in enumerate(insts):
-        with B.Opo([ins], nz, precision="f32", split_order=4) as h:
+        with B.Opo([ins], nz, precision="f32", split_order=4, schedule="two_pass") as h:
             h.cavity_roundtrip(nrt)
             assert np.array_equal(batch[i][0], h.get_fields())
             assert np.array_equal(batch[i][1], h.energy_history())

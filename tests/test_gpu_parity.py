@@ -159,11 +159,11 @@ def test_batch_of_uneven_sizes_equals_singles_and_oracle():
                                  delta=(0.0, 0.1 * b, 0.0))
         insts.append(ins)
     nz, nrt = 8, 3
-    with B.Opo(insts, nz, precision="f32") as hb:
+    with B.Opo(insts, nz, precision="f32", schedule="two_pass") as hb:
         hb.cavity_roundtrip(nrt)
         batch = [(hb.get_fields(i), hb.energy_history(i)) for i in range(len(sizes))]
     for i, ins in enumerate(insts):
-        with _handle(ins, nz, "f32") as h:
+        with _handle(ins, nz, "f32", schedule="two_pass") as h:
             h.cavity_roundtrip(nrt)
             assert np.array_equal(batch[i][0], h.get_fields())
             assert np.array_equal(batch[i][1], h.energy_history())
@@ -243,13 +243,13 @@ def test_mixed_schedule_batch_equals_singles_and_oracle():
                                  delta=(0.0, -0.1 * b, 0.0), eom_beta=0.3, eom_fpm_thz=1.0 / 40.0)
         insts.append(ins)
     nz, nrt = 6, 3
-    with B.Opo(insts, nz, precision="f32") as hb:
+    with B.Opo(insts, nz, precision="f32", schedule="two_pass") as hb:
         hb.cavity_roundtrip(nrt)
         batch = [(hb.get_fields(i), hb.energy_history(i)) for i in range(len(sizes))]
         hb.ssfm_propagate(5, 0.1)
         prop = [hb.get_fields(i) for i in range(len(sizes))]
     for i, ins in enumerate(insts):
-        with _handle(ins, nz, "f32") as h:
+        with _handle(ins, nz, "f32", schedule="two_pass") as h:
             h.cavity_roundtrip(nrt)
             assert np.array_equal(batch[i][0], h.get_fields())
             assert np.array_equal(batch[i][1], h.energy_history())
@@ -275,11 +275,11 @@ def test_mixed_schedule_with_gdd_and_eom():
                                  eom_beta=0.4, eom_fpm_thz=1.0 / 40.0)
         insts.append(ins)
     nz, nrt = 6, 3
-    with B.Opo(insts, nz, precision="f32") as hb:
+    with B.Opo(insts, nz, precision="f32", schedule="two_pass") as hb:
         hb.cavity_roundtrip(nrt)
         batch = [(hb.get_fields(i), hb.energy_history(i)) for i in range(len(sizes))]
     for i, ins in enumerate(insts):
-        with _handle(ins, nz, "f32") as h:
+        with _handle(ins, nz, "f32", schedule="two_pass") as h:
             h.cavity_roundtrip(nrt)
             assert np.array_equal(batch[i][0], h.get_fields())
             assert np.array_equal(batch[i][1], h.energy_history())
@@ -299,11 +299,11 @@ def test_fp64_mixed_schedule_batch():
         ins["cavity"] = W.cavity(resonant=(0, 1, 0), refl=(0.0, 0.8 + 0.03 * b, 0.0), delta=(0.0, 0.2 * b, 0.0))
         insts.append(ins)
     nz, nrt = 6, 3
-    with B.Opo(insts, nz, precision="f64") as hb:
+    with B.Opo(insts, nz, precision="f64", schedule="two_pass") as hb:
         hb.cavity_roundtrip(nrt)
         batch = [(hb.get_fields(i), hb.energy_history(i)) for i in range(len(insts))]
     for i, ins in enumerate(insts):
-        with _handle(ins, nz, "f64") as h:
+        with _handle(ins, nz, "f64", schedule="two_pass") as h:
             h.cavity_roundtrip(nrt)
             assert np.array_equal(batch[i][0], h.get_fields())
             assert np.array_equal(batch[i][1], h.energy_history())

@@ -1,0 +1,280 @@
+"""The resident pass (one workgroup holds an instance for a whole crystal pass and
+its round-trip boundary) against the FP64 oracle, through the C ABI.
+
+Bars as for the two-pass kernels: complex128 to 1e-11 relative L2 per field and
+pass, complex64 to 1e-4 per pass and 1e-3 in round-trip energies. Exact
+equalities hold where the same kernels run on the same data: a resident instance
+in a batch (beside two-pass instances) equals its own single run, graph replay
+equals plain launches, and the adaptive step and the spectrum read-out (which run
+the column and row tiles of every instance) do not depend on the schedule.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import torch  # noqa: F401  (imported at collection: the first import can take minutes)
+
+import oracle
+from paper_2410_02532_amd import opo as B
+from paper_2410_02532_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-11, "f32": 1e-4}
+TOL_E = {"f64": 1e-10, "f32": 1e-3}
+SHAPES = [("f32", 1 << 10), ("f32", 1 << 11), ("f32", 1 << 12), ("f64", 1 << 10), ("f64", 1 << 11)]
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def rel_l2(got, ref):
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def _stress(nt, seed, nf=3, t_window=40.0, dk=0.4):
+    """Pulsed pump, seeded signal (and idler), mismatch, loss, GVM, GVD and TOD."""
+    if nf == 3:
+        cr = W.crystal(nt, t_window_ps=t_window, deff=60.0, b3=(300.0, -150.0, 210.0), dk_per_mm=dk,
+                       alpha=(0.02, 0.01, 0.03), db1=(0.25, 0.0, -0.15), b2=(250.0, 150.0, 100.0),
+                       n=(2.25, 2.2, 2.15))
+    else:
+        cr = W.crystal2(nt, t_window_ps=t_window, deff=60.0, b3=(300.0, -150.0, 0.0), dk_per_mm=dk,
+                        alpha=(0.02, 0.01, 0.0), db1=(0.25, 0.0, 0.0), b2=(250.0, 150.0, 0.0),
+                        n=(2.25, 2.2, 2.2))
+    t = W.time_grid(nt, t_window)
+    pump = 2.0e6 * np.exp(-t * t / (2 * (0.2 * t_window) ** 2)) * np.exp(0.3j)
+    a = np.empty((nf, nt), complex)
+    a[0] = pump
+    a[1] = 3.0e5 * np.exp(-(t - 1.0) ** 2 / (2 * (0.1 * t_window) ** 2)) + W.noise(nt, 1e3, seed + 1)
+    if nf == 3:
+        a[2] = W.noise(nt, 2e4, seed + 2)
+    cav = W.cavity(resonant=(0, 1, 1 if nf == 3 else 0), refl=(0.0, 0.9, 0.7 if nf == 3 else 0.0),
+                   delta=(0.0, 0.2, -0.4 if nf == 3 else 0.0))
+    return dict(crystal=cr, cavity=cav, fields=a, pump_in=pump)
+
+
+def _launches(h):
+    return {k: v[1] for k, v in h.kernel_times().items()}
+
+
+@pytest.mark.parametrize("nf", [3, 2])
+@pytest.mark.parametrize("precision, nt", SHAPES)
+def test_resident_pass_parity(precision, nt, nf):
+    """One pass of 20 steps with every term of Eqs. 2-5, and the same pass in two calls
+    (z continues) bit for bit; only resident launches run."""
+    say("resident pass nt=%d nf=%d %s" % (nt, nf, precision))
+    ins = _stress(nt, seed=nt + nf, nf=nf)
+    nz, dz = 20, 0.25
+    ref = oracle.ssfm_pass(ins["crystal"], ins["fields"], nz, dz)
+    with B.Opo([ins], nz, precision=precision, schedule="resident", profile=True) as h:
+        h.ssfm_propagate(nz, dz)
+        got = h.get_fields()
+        n = _launches(h)
+    assert n["resident_pass"] == 1 and n["column_pass"] == 0 and n["row_pass"] == 0, n
+    for x in range(nf):
+        assert rel_l2(got[x], ref[x]) <= TOL[precision], (x, rel_l2(got[x], ref[x]))
+    with B.Opo([ins], nz, precision=precision, schedule="resident") as h:
+        h.ssfm_propagate(nz // 2, dz)
+        h.ssfm_propagate(nz // 2, dz)
+        assert np.array_equal(h.get_fields(), got)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_resident_round_trips_gdd_eom_pulsed(precision):
+    """Doubly resonant cavity with GDD on both resonant fields, an EOM, detuning, loss and
+    a pulsed pump re-read every round trip: energies and final fields against the oracle."""
+    ins = _stress(2048, seed=5)
+    ins["cavity"] = W.cavity(resonant=(0, 1, 1), refl=(0.0, 0.95, 0.9), delta=(0.0, 0.3, -0.2),
+                             gdd_fs2=-900.0, eom_beta=0.8, eom_fpm_thz=2.0 / 40.0)
+    nz, nrt = 12, 6
+    ref, e_ref = oracle.roundtrips(ins["crystal"], ins["cavity"], ins["fields"], ins["pump_in"], nz, nrt)
+    with B.Opo([ins], nz, precision=precision, schedule="resident") as h:
+        h.cavity_roundtrip(nrt)
+        e = h.energy_history()
+        got = h.get_fields()
+    for x in range(3):
+        assert np.max(np.abs(e[:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E[precision], x
+        assert rel_l2(got[x], ref[x]) <= 10 * TOL[precision], (x, rel_l2(got[x], ref[x]))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_resident_sro_long_run(precision):
+    """CW SRO at 4x threshold from noise, 300 round trips of 25 steps at 2^11 points, through
+    build-up and pump depletion: energies against the oracle."""
+    w = W.config("sro_cw", nt=2048, nz=25, level=4.0)
+    nrt = 300
+    _, e_ref = oracle.roundtrips(w["crystal"], w["cavity"], w["fields"], w["pump_in"], w["nz"], nrt)
+    with B.from_workload(w, precision=precision, schedule="resident") as h:
+        h.cavity_roundtrip(nrt)
+        e = h.energy_history()
+    tol = 1e-9 if precision == "f64" else 1e-3
+    for x in range(3):
+        assert np.max(np.abs(e[:, x] - e_ref[:, x]) / e_ref[:, x]) <= tol, x
+
+
+@pytest.mark.parametrize("nf", [3, 2])
+def test_resident_kerr_and_pump_enhanced(nf):
+    """Kerr crystal with mismatch and every dispersion order, and a resonant pump fed
+    through its mirror (pump-enhanced cavity): 5 round trips against the oracle (FP32).
+    The amplitudes keep the run well conditioned: in the oracle a 1e-7 relative change of
+    the input moves the final fields by 2e-4 (three waves) and 1.5e-5 (two waves); the
+    two-wave case at the three-wave amplitudes is chaotic (a 1e-7 change moves them by
+    order one, and FP32 and FP64 runs of either schedule part ways)."""
+    mk = W.crystal if nf == 3 else W.crystal2
+    nt = 1024
+    cr = mk(nt, t_window_ps=40.0, deff=60.0, b3=(300.0, -150.0, 100.0), dk_per_mm=0.4,
+            alpha=(0.02, 0.01, 0.03), db1=(0.25, 0.0, -0.15), b2=(250.0, 150.0, 100.0))
+    cr["n2_m2_per_w"] = 2e-17 if nf == 3 else 4e-17
+    p0, s0 = (2.0e7, 3.0e6) if nf == 3 else (5.0e6, 1.0e6)
+    t = W.time_grid(nt, 40.0)
+    a = np.empty((nf, nt), complex)
+    a[0] = p0 * np.exp(-t * t / (2 * 8.0 ** 2)) * np.exp(0.3j)
+    a[1] = s0 * np.exp(-(t - 1.0) ** 2 / (2 * 4.0 ** 2)) + W.noise(nt, 1e4, 3)
+    if nf == 3:
+        a[2] = W.noise(nt, 2e5, 4)
+    cav = W.cavity(resonant=(1, 1, 0), refl=(0.6, 0.8, 0.0), delta=(0.1, 0.2, 0.0))
+    ins = dict(crystal=cr, cavity=cav, fields=a, pump_in=a[0].copy())
+    nz, nrt = 50, 5                     # kappa |A| dz = 0.32 (the init step criterion)
+    ref, e_ref = oracle.roundtrips(cr, cav, a, ins["pump_in"], nz, nrt)
+    with B.Opo([ins], nz, precision="f32", schedule="resident") as h:
+        h.cavity_roundtrip(nrt)
+        e = h.energy_history()
+        got = h.get_fields()
+    for x in range(nf):
+        assert np.max(np.abs(e[:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E["f32"], x
+        assert rel_l2(got[x], ref[x]) <= 10 * TOL["f32"], (x, rel_l2(got[x], ref[x]))
+
+
+def test_resident_windowed_pump_and_record():
+    """Long pump read one window per round trip and the record of the fields leaving the
+    crystal, against the oracle."""
+    nt, nz, windows, nrt = 1024, 10, 8, 10
+    g = np.random.Generator(np.random.PCG64(9))
+    t = W.time_grid(nt)
+    env = np.exp(-((np.arange(windows) - windows / 2) / (windows / 3)) ** 2)
+    pump = (2.0e6 * env[:, None] * np.exp(-t[None, :] ** 2 / (2 * 30.0 ** 2))
+            * np.exp(1j * g.uniform(0, 2 * np.pi, size=(windows, 1))))
+    f = W.initial_fields(nt, 2.0e6, 9)
+    f[1] += W.noise(nt, 1e4, 14)
+    f[0] = pump[0]
+    ins = dict(crystal=W.crystal(nt, deff=40.0), cavity=W.cavity(refl=(0.0, 0.8, 0.0)), fields=f,
+               pump_in=pump)
+    _, e_ref, rec_ref = oracle.roundtrips_record(ins["crystal"], ins["cavity"], f, pump, nz, nrt)
+    with B.Opo([ins], nz, precision="f32", record_rt=nrt, schedule="resident") as h:
+        h.cavity_roundtrip(4)
+        h.cavity_roundtrip(nrt - 4)
+        e = h.energy_history()
+        rec = [h.record(m) for m in range(nrt)]
+    for m in range(nrt):
+        for x in range(3):
+            if not np.any(rec_ref[m, x]):
+                assert not np.any(rec[m][x]), (m, x)
+                continue
+            assert rel_l2(rec[m][x], rec_ref[m, x]) <= TOL["f32"], (m, x)
+    for x in range(3):
+        live = e_ref[:, x] > 0.0
+        assert np.max(np.abs(e[live, x] - e_ref[live, x]) / e_ref[live, x]) <= TOL["f32"], x
+        assert np.all(e[~live, x] == 0.0)
+
+
+def _mixed_batch():
+    insts = []
+    for b, (nt, nf) in enumerate([(4096, 3), (1024, 2), (8192, 3), (2048, 3), (16384, 3), (4096, 2),
+                                  (1024, 3), (8192, 2)]):
+        ins = _stress(nt, seed=60 + b, nf=nf)
+        ins["cavity"] = W.cavity(resonant=(0, 1, 0), refl=(0.0, 0.85 + 0.01 * b, 0.0),
+                                 delta=(0.0, 0.05 * b, 0.0), eom_beta=0.3, eom_fpm_thz=1.0 / 40.0)
+        insts.append(ins)
+    return insts
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_resident_beside_two_pass_equals_singles(precision):
+    """Resident and two-pass instances (three and two waves) in one handle: round trips
+    (graph and plain launches) and a pass after them; every instance equals its own single
+    run bit for bit, and the oracle."""
+    insts = _mixed_batch()
+    nz, nrt = 6, 3
+    runs = {}
+    for graph in (True, False):
+        with B.Opo(insts, nz, precision=precision, schedule="resident", use_graph=graph) as hb:
+            hb.cavity_roundtrip(nrt)
+            batch = [(hb.get_fields(i), hb.energy_history(i)) for i in range(len(insts))]
+            hb.ssfm_propagate(5, 0.1)
+            prop = [hb.get_fields(i) for i in range(len(insts))]
+        runs[graph] = (batch, prop)
+    for i in range(len(insts)):
+        for k in range(2):
+            assert np.array_equal(runs[True][0][i][k], runs[False][0][i][k]), i
+        assert np.array_equal(runs[True][1][i], runs[False][1][i]), i
+    batch, prop = runs[True]
+    for i, ins in enumerate(insts):
+        with B.Opo([ins], nz, precision=precision, schedule="resident") as h:
+            h.cavity_roundtrip(nrt)
+            assert np.array_equal(batch[i][0], h.get_fields()), i
+            assert np.array_equal(batch[i][1], h.energy_history()), i
+            h.ssfm_propagate(5, 0.1)
+            assert np.array_equal(prop[i], h.get_fields()), i
+        ref, e_ref = oracle.roundtrips(ins["crystal"], ins["cavity"], ins["fields"], ins["pump_in"], nz, nrt)
+        nf = ref.shape[0]
+        for x in range(nf):
+            assert rel_l2(batch[i][0][x], ref[x]) <= 10 * TOL[precision], (i, x)
+            assert np.max(np.abs(batch[i][1][:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E[precision], (i, x)
+
+
+def test_resident_profile_counts_and_auto_schedule():
+    """The profile option times the resident launches as their own class (one per shape and
+    round trip); the automatic schedule runs a batch's 2^10..2^12 instances resident and an
+    instance alone in two passes."""
+    insts = _mixed_batch()
+    with B.Opo(insts, 6, precision="f32", schedule="resident", profile=True) as h:
+        h.cavity_roundtrip(2)
+        n = _launches(h)
+    # one timed group of resident launches per round trip (shapes (log2 nt, nf) served:
+    # (12, 3), (11, 3), (10, 3), (12, 2), (10, 2))
+    assert n["resident_pass"] == 2, n
+    with B.Opo(insts, 6, precision="f32", profile=True) as h:
+        h.cavity_roundtrip(1)
+        assert _launches(h)["resident_pass"] > 0
+    with B.Opo([insts[0]], 6, precision="f32", profile=True) as h:
+        h.cavity_roundtrip(1)
+        n = _launches(h)
+        assert n["resident_pass"] == 0 and n["column_pass"] > 0, n
+
+
+def test_resident_nonfinite_stops_with_the_last_finite_state():
+    """A NaN set into a resident instance of a batch: the call stops in its first round trip
+    with no row appended and the fields as they were set."""
+    insts = _mixed_batch()
+    with B.Opo(insts, 6, precision="f32", schedule="resident") as h:
+        h.cavity_roundtrip(2)
+        before = [h.get_fields(i) for i in range(len(insts))]
+        bad = before[1].copy()
+        bad[1, 5] = np.nan
+        h.set_fields(bad, 1)
+        with pytest.raises(B.OpoError) as ei:
+            h.cavity_roundtrip(3)
+        assert ei.value.code == B.OPO_ENONFINITE
+        assert h.energy_history(0).shape == (2, 3)
+        assert np.array_equal(h.get_fields(1), bad, equal_nan=True)
+        for i in (0, 2, 3):
+            assert np.array_equal(h.get_fields(i), before[i]), i
+
+
+def test_adaptive_and_spectrum_do_not_depend_on_the_schedule():
+    """The adaptive step and the spectrum read-out run the column and row tiles of every
+    instance, resident or not: the same results under both schedules."""
+    insts = [_stress(nt, seed=80 + b) for b, nt in enumerate((1024, 4096, 8192))]
+    out = {}
+    for sched in ("two_pass", "resident"):
+        with B.Opo(insts, 10, precision="f64", schedule=sched) as h:
+            acc, rej, zend = h.ssfm_propagate_adaptive(1.0, 1e-6, 0.05)
+            out[sched] = ([h.get_fields(i) for i in range(3)], [h.get_fields(i, domain=1) for i in range(3)],
+                          acc, rej)
+    for i in range(3):
+        assert np.array_equal(out["two_pass"][0][i], out["resident"][0][i]), i
+        assert np.array_equal(out["two_pass"][1][i], out["resident"][1][i]), i
+    assert np.array_equal(out["two_pass"][2], out["resident"][2])

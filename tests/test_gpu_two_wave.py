@@ -96,13 +96,13 @@ def test_two_and_three_wave_instances_share_a_batch():
                                  delta=(0.0, -0.1 * b, 0.0), eom_beta=0.3, eom_fpm_thz=1.0 / 40.0)
         insts.append(ins)
     nz, nrt = 6, 3
-    with B.Opo(insts, nz, precision="f32") as hb:
+    with B.Opo(insts, nz, precision="f32", schedule="two_pass") as hb:
         hb.cavity_roundtrip(nrt)
         batch = [(hb.get_fields(i), hb.energy_history(i)) for i in range(len(insts))]
     for i, ins in enumerate(insts):
         nf = ins["crystal"].get("nf", 3)
         assert batch[i][0].shape == (nf, ins["crystal"]["nt"])
-        with B.Opo([ins], nz, precision="f32") as h:
+        with B.Opo([ins], nz, precision="f32", schedule="two_pass") as h:
             h.cavity_roundtrip(nrt)
             assert np.array_equal(batch[i][0], h.get_fields())
             assert np.array_equal(batch[i][1], h.energy_history())
