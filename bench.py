@@ -226,7 +226,7 @@ def picks_per_size(w, by_level=False):
 
 # ---------------------------------------------------------------- roofline --
 
-def roofline(w, precision, n_rt):
+def roofline(w, precision, n_rt, graph_rt_s=None):
     """Roofline of the dominant kernel from per-launch device times (HIP events around every
     launch on the handle's stream, profile option).
 
@@ -243,7 +243,9 @@ def roofline(w, precision, n_rt):
         h.cavity_roundtrip(n_rt)
         after = h.kernel_times()
     per = {k: (after[k][0] - before[k][0], after[k][1] - before[k][1]) for k in after}
-    dom = max(("column_pass", "row_pass", "mixed_pass"), key=lambda k: per[k][0])
+    dom = max(("column_pass", "row_pass", "mixed_pass", "resident_pass"), key=lambda k: per[k][0])
+    if dom == "resident_pass":
+        return resident_roofline(w, precision, per, two_pass, graph_rt_s)
     ms, launches = per[dom]
     insts = [instances_of(w)[i] for i in two_pass]
     bytes_per_launch = sum(BYTES_PER_FIELD[precision] * nf_of(i) * i["crystal"]["nt"] for i in insts) / 2
@@ -262,6 +264,34 @@ def roofline(w, precision, n_rt):
                  "peak": VALU_PEAK_TFLOPS, "frac": round(tflops / VALU_PEAK_TFLOPS, 5),
                  "peak_nonpacked": VALU_NONPACKED_TFLOPS,
                  "frac_nonpacked": round(tflops / VALU_NONPACKED_TFLOPS, 5)},
+        "kernel_ms": {k: round(v[0], 3) for k, v in per.items()},
+        "launches": {k: v[1] for k, v in per.items()},
+        "instances_covered": len(insts),
+    }
+
+
+def resident_roofline(w, precision, per, two_pass, graph_rt_s):
+    """Roofline of the resident launches when they dominate (all instances small). The
+    resident launches of a round trip (one per shape) cover nz field-point-steps of every
+    resident point and keep the fields on chip: their HBM traffic is one read and one write
+    of the fields per round trip, far below the two-pass minimum, so the line is priced
+    against the non-packed FP32 VALU peak (no packed FP32 in this build: 256 CUs x 4 SIMDs
+    x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s). The time is the graph-timed round trip
+    when given (the shapes run side by side there; the profile option serializes them),
+    else the profile option's time per round trip."""
+    ms, groups = per["resident_pass"]
+    insts = [ins for i, ins in enumerate(instances_of(w)) if i not in set(two_pass)]
+    flops = sum(i["crystal"]["nt"] * w["nz"] * flops_per_unit(i["crystal"]["nt"], nf_of(i)) for i in insts)
+    hbm = sum(BYTES_PER_FIELD[precision] * nf_of(i) * i["crystal"]["nt"] for i in insts)
+    avg_s = graph_rt_s if graph_rt_s else ms / 1e3 / groups
+    tflops = flops / avg_s / 1e12
+    return {
+        "bound": "alu", "kernel": "resident_pass", "achieved": round(tflops, 3), "peak": VALU_NONPACKED_TFLOPS,
+        "unit": "TFLOP/s", "frac": round(tflops / VALU_NONPACKED_TFLOPS, 5), "traffic": None,
+        "flops_per_round_trip": round(flops), "avg_round_trip_us": round(avg_s * 1e6, 3),
+        "serialized_round_trip_us": round(ms / groups * 1e3, 3),
+        "frac_packed_peak": round(tflops / VALU_PEAK_TFLOPS, 5),
+        "hbm_bytes_per_round_trip": round(hbm), "hbm_gbs": round(hbm / avg_s / 1e9, 2),
         "kernel_ms": {k: round(v[0], 3) for k, v in per.items()},
         "launches": {k: v[1] for k, v in per.items()},
         "instances_covered": len(insts),
@@ -451,10 +481,9 @@ def main():
             for i in picks_per_size(dsw):
                 jobs.submit(("deg_pass", i), ("pass", "degenerate_sweep", {}, i, None))
                 jobs.submit(("deg_rt", i), ("rt", "degenerate_sweep", {}, i, 3))
-            small = dict(min_log2=10, max_log2=12)
-            for i in picks_per_size(W.config("batched_sweep", **small), by_level=True):
-                jobs.submit(("small_pass", i), ("pass", "batched_sweep", small, i, None))
-                jobs.submit(("small_rt", i), ("rt", "batched_sweep", small, i, 3))
+            for i in picks_per_size(W.config("small_sweep"), by_level=True):
+                jobs.submit(("small_pass", i), ("pass", "small_sweep", {}, i, None))
+                jobs.submit(("small_rt", i), ("rt", "small_sweep", {}, i, 3))
             for i in range(3):
                 jobs.submit(("ns_pass", i), ("pass", "ns_pulsed", {}, i, None))
                 jobs.submit(("ns_rt", i), ("rt", "ns_pulsed", {}, i, 30))
@@ -486,7 +515,7 @@ def main():
                    "wall_s": round(wall_s, 4)},
     }
     if not args.no_roofline:
-        line["roofline"] = roofline(w, args.precision, min(steps, 100))
+        line["roofline"] = roofline(w, args.precision, min(steps, 100), graph_rt_s=dev_s / steps)
         print("roofline: %s" % json.dumps(line["roofline"]), file=sys.stderr, flush=True)
 
     var = {}
@@ -543,7 +572,7 @@ def main():
         # the paper's small grids: 256 instances of 2^10..2^12 points, where every instance
         # runs resident (one workgroup per instance for the whole round trip) under the
         # automatic schedule, against the same batch on two passes per z-step
-        ws = W.config("batched_sweep", min_log2=10, max_log2=12)
+        ws = W.config("small_sweep")
         n = 100
         d, _, hs = run_gpu(ws, n, 5, "f32", keep=picks_per_size(ws, by_level=True))
         d2, _, _ = run_gpu(ws, n, 5, "f32", schedule="two_pass")
@@ -627,7 +656,7 @@ def main():
             ee = [energy_errors(hs[i], jobs.get(("deg_rt", i)), [0, 1, 2]) for i in dp]
             v["short_run"] = {"round_trips": 3, "signal_power_rel": max(x[0] for x in ee),
                               "energy_rel_all_fields": max(x[1] for x in ee)}
-            ws = W.config("batched_sweep", min_log2=10, max_log2=12)
+            ws = W.config("small_sweep")
             v = var["f32_small_sweep_2^10..2^12"]
             hs = v.pop("_hist")
             sp = picks_per_size(ws, by_level=True)

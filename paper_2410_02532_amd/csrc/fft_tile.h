@@ -18,6 +18,7 @@
 // reused for every transform the thread owns.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 namespace opo {
 
@@ -256,10 +257,14 @@ template <int N, int PF, int P, int R16 = 2048> __host__ __device__ constexpr in
 // One stage over NTR transforms held by this thread. Position n of transform
 // tr lives at LDS element base[tr] + n*LS; t is the thread's index in its
 // transform.
-template <typename R, int N, int PF, int NTR, int DIR, int LS, int RS, int P>
+template <typename R, int N, int PF, int NTR, int DIR, int LS, int RS, int P, bool LIN>
 __device__ __forceinline__ void reg_stage(cplx<R> (&v)[NTR][PF], cplx<R> *lds, const int (&base)[NTR],
                                           int t, const Phasor<R> *__restrict__ tw)
 {
+    // LDS element of position e: padded by lds_index, or as given when the layout
+    // is already padded by the caller (LIN: linear in e, so that the offsets of a
+    // thread's positions are compile-time constants)
+    auto at = [](int e) { return LIN ? e : lds_index<R>(e); };
     using V = cplx<R>;
     constexpr int NBT = PF / RS;       // butterflies per thread and transform
     constexpr int STRIDE = N / PF;     // distance between a thread's samples
@@ -299,7 +304,7 @@ __device__ __forceinline__ void reg_stage(cplx<R> (&v)[NTR][PF], cplx<R> *lds, c
                 const int j = (i - k) * RS + k;
 #pragma unroll
                 for (int r = 0; r < RS; ++r)
-                    lds[lds_index<R>(base[tr] + (j + r * P) * LS)] = x[r];
+                    lds[at(base[tr] + (j + r * P) * LS)] = x[r];
             }
         }
     }
@@ -309,19 +314,19 @@ __device__ __forceinline__ void reg_stage(cplx<R> (&v)[NTR][PF], cplx<R> *lds, c
         for (int tr = 0; tr < NTR; ++tr)
 #pragma unroll
             for (int m = 0; m < PF; ++m)
-                v[tr][m] = lds[lds_index<R>(base[tr] + (t + m * STRIDE) * LS)];
+                v[tr][m] = lds[at(base[tr] + (t + m * STRIDE) * LS)];
         lds_sync();
     }
 }
 
-template <typename R, int N, int PF, int NTR, int DIR, int LS, int P, int R16>
+template <typename R, int N, int PF, int NTR, int DIR, int LS, int P, int R16, bool LIN>
 __device__ __forceinline__ void reg_fft_from(cplx<R> (&v)[NTR][PF], cplx<R> *lds, const int (&base)[NTR],
                                              int t, const Phasor<R> *__restrict__ tw)
 {
     if constexpr (P < N) {
         constexpr int RS = stage_radix<N, PF, P, R16>();
-        reg_stage<R, N, PF, NTR, DIR, LS, RS, P>(v, lds, base, t, tw);
-        reg_fft_from<R, N, PF, NTR, DIR, LS, P * RS, R16>(v, lds, base, t, tw);
+        reg_stage<R, N, PF, NTR, DIR, LS, RS, P, LIN>(v, lds, base, t, tw);
+        reg_fft_from<R, N, PF, NTR, DIR, LS, P * RS, R16, LIN>(v, lds, base, t, tw);
     }
 }
 
@@ -329,12 +334,13 @@ __device__ __forceinline__ void reg_fft_from(cplx<R> (&v)[NTR][PF], cplx<R> *lds
 // length N. On entry and on exit v[tr][m] is sample t + m*(N/PF). Every
 // thread of the workgroup must call it (it synchronizes the workgroup when
 // N > PF). LS is the LDS element stride between consecutive positions; radix-16
-// stages serve transforms of up to R16 points.
-template <typename R, int N, int PF, int NTR, int DIR, int LS, int R16 = 2048>
+// stages serve transforms of up to R16 points. LIN: base and LS already lay the
+// positions out without bank conflicts (no lds_index padding).
+template <typename R, int N, int PF, int NTR, int DIR, int LS, int R16 = 2048, bool LIN = false>
 __device__ __forceinline__ void reg_fft(cplx<R> (&v)[NTR][PF], cplx<R> *lds, const int (&base)[NTR], int t,
                                         const Phasor<R> *__restrict__ tw)
 {
-    reg_fft_from<R, N, PF, NTR, DIR, LS, 1, R16>(v, lds, base, t, tw);
+    reg_fft_from<R, N, PF, NTR, DIR, LS, 1, R16, LIN>(v, lds, base, t, tw);
 }
 
 // The same transforms stage by stage through one transform's worth of LDS:

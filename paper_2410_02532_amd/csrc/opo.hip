@@ -872,9 +872,10 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
             d.pump_off = pump_elems;
             pump_elems += static_cast<long long>(d.nt) * d.pump_windows;
         }
-        // LDS of a tile: nf fields of `cols` columns, or `rows` rows
+        // LDS of a tile: nf fields of `cols` columns in rows of cols + 1 elements
+        // (col_lds_row), or `rows` rows
         const bool seq = opt.precision == OPO_F64 ? col_seq_lds<double>(p.log2n2) : col_seq_lds<float>(p.log2n2);
-        max_a = std::max(max_a, static_cast<size_t>(seq ? 1 : d.nf) * d.cols * d.n2);
+        max_a = std::max(max_a, static_cast<size_t>(seq ? 1 : d.nf) * (d.cols + 1) * d.n2);
         max_b = std::max(max_b, static_cast<size_t>(d.rows) * d.n1);
         // shapes the kernels are instantiated for
         const int max_ln1 = opt.precision == OPO_F64 ? kMaxLog2N1<double> : kMaxLog2N1<float>;
@@ -1109,8 +1110,7 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
                 return bail(fail(OPO_EDEVICE, "creating the resident branches' streams and events failed"));
     }
 
-    h->lds_a = (opt.precision == OPO_F64 ? lds_elems<double>(static_cast<int>(max_a))
-                                         : lds_elems<float>(static_cast<int>(max_a))) * es;
+    h->lds_a = max_a * es;
     h->lds_b = (opt.precision == OPO_F64 ? lds_elems<double>(static_cast<int>(max_b))
                                          : lds_elems<float>(static_cast<int>(max_b))) * es;
     if (h->lds_a > 160 * 1024 || h->lds_b > 160 * 1024)

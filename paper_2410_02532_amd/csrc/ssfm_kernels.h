@@ -140,6 +140,15 @@ template <typename R> struct StepArgs {
     const cplx<R> *src;
 };
 
+// Element q of the array at base, q formed in 32 bits (below 2^28 within one
+// instance's arrays): the address is a uniform 64-bit base plus a 32-bit
+// per-lane byte offset, which the loads and stores take directly.
+template <typename T> __device__ __forceinline__ T &el32(T *base, unsigned q)
+{
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return *reinterpret_cast<T *>(reinterpret_cast<B *>(base) + q * static_cast<unsigned>(sizeof(T)));
+}
+
 // ---------------------------------------------------------------- shapes --
 // Column tile for columns of length 2^ln2: PF samples per thread and field,
 // COLS columns so that COLS * sizeof(complex) = 128 B (one cache line), and
@@ -160,6 +169,11 @@ template <typename R> __host__ __device__ constexpr int col_cols(int ln2)
 {
     return kThreads * col_pf<R>(ln2) >> ln2;
 }
+// LDS layout of a column tile: position p of column c of field f at element
+// f*(COLS + 1)*n2 + p*(COLS + 1) + c. The spare element per row of COLS shifts
+// consecutive positions by one element across the banks, and every offset
+// between a thread's positions is a compile-time constant.
+template <typename R> __host__ __device__ constexpr int col_lds_row(int ln2) { return col_cols<R>(ln2) + 1; }
 // Column tiles whose fields would need more than 32 KB of LDS for one
 // exchange pass their fields through it one at a time (a single field's
 // worth of LDS), so that several workgroups still fit a CU.
@@ -169,17 +183,23 @@ template <typename R> __host__ __device__ constexpr bool col_seq_lds(int ln2)
 }
 
 // Row tile for rows of length 2^ln1: PF samples per thread, at least 16
-// threads (128 B) along a row, ROWS rows per tile. FP32 rows of 1024 points
-// and more take 16 samples, for radix-16 stages: one stage and one LDS
-// exchange fewer than radix 8. (At 256 points the tiles of four times the
-// rows halve the workgroups of a single instance, whose launches are then
-// too few to fill the chip; in FP64 the registers are better spent on
-// occupancy.)
+// threads (128 B) along a row, ROWS rows per tile. FP32 rows of 4096 points
+// take 16 samples (radix-16 stages, one row per workgroup). Rows of 1024 and
+// 2048 points take 8: with 16 their radix-16 stages held the mixed kernel at
+// 128 VGPRs (four workgroups per CU, one register spilled); with 8 it needs 95
+// and five fit, and the batched sweep runs 6 % faster (3.42e10 -> 3.63e10;
+// a batch of 2^16 instances alone 4 % slower, 3.24e10 -> 3.10e10). (At 256
+// points the tiles of four times the rows halve the workgroups of a single
+// instance, whose launches are then too few to fill the chip; in FP64 the
+// registers are better spent on occupancy.)
+#ifndef OPO_ROW_R16_MIN
+#define OPO_ROW_R16_MIN 4096
+#endif
 template <typename R> __host__ __device__ constexpr int row_pf(int ln1)
 {
     const int n = 1 << ln1;
     if (n == 1) return 1;
-    if (sizeof(R) == 4 && n >= 1024) return n / 16 > kThreads ? n / kThreads : 16;
+    if (sizeof(R) == 4 && n >= OPO_ROW_R16_MIN) return n / 16 > kThreads ? n / kThreads : 16;
     int pf = n / 16;
     pf = pf < 2 ? 2 : pf;
     pf = pf > 8 ? 8 : pf;
@@ -461,6 +481,7 @@ __device__ __forceinline__ void column_fft(cplx<R> (&v)[NF][PF], cplx<R> *s, con
                                            const Phasor<R> *__restrict__ tw)
 {
     constexpr int N = 1 << LN2;
+    constexpr int ROW = COLS + 1;   // col_lds_row
     if constexpr (N > 1 && col_seq_lds<R>(LN2)) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -468,12 +489,12 @@ __device__ __forceinline__ void column_fft(cplx<R> (&v)[NF][PF], cplx<R> *s, con
 #pragma unroll
             for (int m = 0; m < PF; ++m) w[0][m] = v[f][m];
             const int b1[1] = {base[0]};
-            reg_fft<R, N, PF, 1, DIR, COLS>(w, s, b1, t, tw);
+            reg_fft<R, N, PF, 1, DIR, ROW, 2048, true>(w, s, b1, t, tw);
 #pragma unroll
             for (int m = 0; m < PF; ++m) v[f][m] = w[0][m];
         }
     } else {
-        reg_fft<R, N, PF, NF, DIR, COLS>(v, s, base, t, tw);
+        reg_fft<R, N, PF, NF, DIR, ROW, 2048, true>(v, s, base, t, tw);
     }
 }
 
@@ -496,8 +517,12 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     // a round trip of this call had non-finite energies: compute, store nothing
     // (the flag is first needed at the stores, so its load hides behind the field loads)
     const bool stopped = a.counter[2] != 0;
-    V *g = a.state + d.off + j1;
-    const V *gs = (a.src ? a.src : a.state) + d.off + j1;
+    // sample m of field f of this thread's column: q0 + m*cstep + f*nt from the
+    // instance's first sample (uniform bases, 32-bit offsets)
+    V *g = a.state + d.off;
+    const V *gs = (a.src ? a.src : a.state) + d.off;
+    const unsigned q0 = static_cast<unsigned>(j1 + n1 * t);
+    const unsigned cstep = static_cast<unsigned>(n1 * T);
 
     double dz = a.dz_arg > 0.0 ? a.dz_arg : d.length_mm / a.nz;
     double zb = a.dz_arg > 0.0 ? a.zbase : 0.0;
@@ -514,31 +539,28 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     // (nt, n1) where it is used (before the inverse and after the forward
     // column FFT) rather than held in registers; the COLS columns of a row of
     // the table are adjacent, and the tables of a batch stay in L2
-    const Phasor<R> *w4t = a.w4tab + d.w4_off + j1;
-    auto w4 = [&](int m) {
-        return act ? w4t[static_cast<long long>(t + m * T) * n1] : make_phasor<R>(1.0, 0.0);
-    };
+    const Phasor<R> *w4t = a.w4tab + d.w4_off;
+    auto w4 = [&](int m) { return act ? el32(w4t, q0 + m * cstep) : make_phasor<R>(1.0, 0.0); };
 #pragma unroll
     for (int f = 0; f < NF; ++f)
 #pragma unroll
         for (int m = 0; m < PF; ++m)
-            v[f][m] = act ? gs[static_cast<long long>(f) * nt + static_cast<long long>(n1) * (t + m * T)]
-                          : mk<V>(R(0), R(0));
+            v[f][m] = act ? el32(gs, q0 + m * cstep + f * nt) : mk<V>(R(0), R(0));
     // the state this round trip starts from (time samples: A_REFRESH never
     // follows an inverse transform), kept to restore after a non-finite one
     if ((flags & A_REFRESH) && a.snap != nullptr && act && !stopped) {
-        V *sp = a.snap + d.off + j1;
+        V *sp = a.snap + d.off;
 #pragma unroll
         for (int f = 0; f < NF; ++f)
 #pragma unroll
             for (int m = 0; m < PF; ++m)
-                sp[static_cast<long long>(f) * nt + static_cast<long long>(n1) * (t + m * T)] = v[f][m];
+                el32(sp, q0 + m * cstep + f * nt) = v[f][m];
     }
 
     int base[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f)
-        base[f] = f * COLS * N + c;
+        base[f] = f * (COLS + 1) * N + c;
     if (flags & A_INV) {
         if constexpr (N > 1) {
 #pragma unroll
@@ -561,12 +583,12 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     const int rt = (flags & (A_REFRESH | A_ENERGY)) ? a.counter[1] : 0;
     const bool rec = (flags & A_ENERGY) && a.record != nullptr && rt < a.record_cap && act && !stopped;
     bool nonfinite = false;              // a boundary value about to be stored is NaN or Inf
-    V *rg = rec ? a.record + static_cast<long long>(rt) * a.record_stride + d.off + j1 : nullptr;
+    V *rg = rec ? a.record + static_cast<long long>(rt) * a.record_stride + d.off : nullptr;
     long long pwin = 0;                  // offset of the input-pump window, -1 = past the last
     if (d.pump_windows > 1) pwin = rt < d.pump_windows ? static_cast<long long>(rt) * nt : -1;
 #pragma unroll
     for (int m = 0; m < PF; ++m) {
-        const long long j = static_cast<long long>(j1) + static_cast<long long>(n1) * (t + m * T);
+        const unsigned j = q0 + m * cstep;   // time index of the sample
         V y0 = v[0][m], y1 = v[1][m], y2 = v[NF - 1][m];
         if (flags & A_RK_PREV) rk4_fields<R, NF>(*cpl, 0, imag, kerr, y0, y1, y2);
         if ((flags & A_ENERGY) && act) {
@@ -575,10 +597,9 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
             if constexpr (NF == 3) en[2] += static_cast<double>(y2.x) * y2.x + static_cast<double>(y2.y) * y2.y;
         }
         if (rec) {
-            const long long q = static_cast<long long>(n1) * (t + m * T);
-            rg[q] = y0;
-            rg[nt + q] = y1;
-            if constexpr (NF == 3) rg[2LL * nt + q] = y2;
+            el32(rg, j) = y0;
+            el32(rg, j + nt) = y1;
+            if constexpr (NF == 3) el32(rg, j + 2 * nt) = y2;
         }
         if (flags & A_MIRROR) {
             if (d.res_mask & 1) y0 = pmul(y0, make_phasor<R>(d.mirror[0][0], d.mirror[0][1]));
@@ -597,7 +618,7 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
         }
         if (flags & A_REFRESH) {
             V pin = pcw;                 // input pump sample of this round trip
-            if (d.pump_off >= 0) pin = (act && pwin >= 0) ? a.pump[d.pump_off + pwin + j] : mk<V>(R(0), R(0));
+            if (d.pump_off >= 0) pin = (act && pwin >= 0) ? el32(a.pump + d.pump_off + pwin, j) : mk<V>(R(0), R(0));
             if (!(d.res_mask & 1)) y0 = pin;
             else if (d.inject != 0.0) y0 = cadd(y0, pmul(pin, make_phasor<R>(d.inject, 0.0)));
             if (!(d.res_mask & 2)) y1 = mk<V>(R(0), R(0));
@@ -637,7 +658,7 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
         for (int f = 0; f < NF; ++f)
 #pragma unroll
             for (int m = 0; m < PF; ++m)
-                g[static_cast<long long>(f) * nt + static_cast<long long>(n1) * (t + m * T)] = v[f][m];
+                el32(g, q0 + m * cstep + f * nt) = v[f][m];
     }
 }
 
@@ -761,13 +782,16 @@ constexpr int kRowRanges[][2] = {{0, 5}, {6, 11}, {12, 12}};
 // every instance runs on XCD t mod 8 (workgroups are dealt to the eight XCDs
 // round robin): each XCD's L2 then holds one eighth of a shared propagator
 // table instead of all of it.
-// Workgroups per CU the mixed kernel is compiled for: four (at most 128
-// VGPRs) for FP32 columns of up to 64 points, which fit that without spills,
-// else whatever the registers allow. (Five for two waves spills a few
-// registers and runs no faster.)
+// Workgroups per CU the mixed kernel is compiled for: at least four (at most
+// 128 VGPRs) for FP32 columns of up to 64 points, else whatever the registers
+// allow. (The kernel for columns of up to 64 points and rows of up to 2048
+// now needs 95 VGPRs; asking for five changes nothing.)
+#ifndef OPO_MIXED_MIN_BLOCKS
+#define OPO_MIXED_MIN_BLOCKS 4
+#endif
 template <typename R, int CR, int RR> constexpr int mixed_min_blocks()
 {
-    return sizeof(R) == 4 && CR == 0 && RR <= 1 ? 4 : 1;
+    return sizeof(R) == 4 && CR == 0 && RR <= 1 ? OPO_MIXED_MIN_BLOCKS : 1;
 }
 
 constexpr int kNoTile = -2147483647 - 1;

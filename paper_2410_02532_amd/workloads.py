@@ -204,6 +204,10 @@ def config(name, **over):
                              pump_in=np.full(nt, ap0 + 0j)))
         return dict(name=name, instances=inst, nz=over.get("nz", 100),
                     n_rt=over.get("n_rt", 500), precision="f32", levels=levels.tolist())
+    if name == "small_sweep":          # the batched sweep over the paper's small grids 2^10..2^12
+        w = config("batched_sweep", **dict(dict(min_log2=10, max_log2=12), **over))
+        w["name"] = name
+        return w
     if name == "degenerate_cw":        # two-wave degenerate CW oscillator, Nt = 2^14
         nt = over.get("nt", 1 << 14)
         level = over.get("level", 3.0)
