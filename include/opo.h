@@ -142,11 +142,13 @@ typedef struct {
     int32_t schedule;       /* how fixed-step passes run:
                                0 = automatic: per instance from a built-in table
                                keyed by precision, field count, nt and whether the
-                               handle holds one instance or several, chosen by
-                               timing the candidates on MI355X (the same shape
-                               always gets the same schedule; an instance alone
-                               and the same instance in a batch may differ in
-                               rounding);
+                               handle's fields fill the chip (at least 2^20
+                               complex samples in all: batch entries) or not
+                               (one instance or a few), chosen by timing the
+                               candidates on MI355X (one shape in one kind of
+                               handle always gets the same schedule; an instance
+                               alone and the same instance in a full batch may
+                               differ in rounding);
                                1 = two passes per z-step (column and row tiles of
                                a four-step FFT) for every instance;
                                2 = resident where served: one workgroup holds an

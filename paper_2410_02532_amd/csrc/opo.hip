@@ -855,12 +855,16 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     std::vector<int> tile_a_inst, tile_b_inst;
     size_t max_a = 0, max_b = 0;
     h->inst.resize(n);
+    // the table's batch entries apply when the handle's fields fill the chip
+    long long total_points = 0;
+    for (int i = 0; i < n; ++i) total_points += static_cast<long long>(nfields(f[i])) * f[i].nt;
+    const bool batched = total_points >= kBatchPoints;
     for (int i = 0; i < n; ++i) {
         InstDesc &d = h->inst[i];
         // schedule: the table's entry for this shape (schedule 0), or two-pass
         // (1) / resident where served (2); an explicit col_log2 sets the split
         const int l2 = ilog2(f[i].nt);
-        const Schedule sc = opt.schedule == 0 ? schedule_lookup(opt.precision == OPO_F64, nfields(f[i]), l2, n > 1)
+        const Schedule sc = opt.schedule == 0 ? schedule_lookup(opt.precision == OPO_F64, nfields(f[i]), l2, batched)
                                               : Schedule{0, opt.schedule == 2 ? 1 : 0};
         const Plan p = make_plan(f[i].nt, opt.precision, opt.col_log2 != 0 ? opt.col_log2 : sc.col_log2);
         fill_desc(d, f[i], c[i * K], k[i], p);
@@ -875,7 +879,8 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         // LDS of a tile: nf fields of `cols` columns in rows of cols + 1 elements
         // (col_lds_row), or `rows` rows
         const bool seq = opt.precision == OPO_F64 ? col_seq_lds<double>(p.log2n2) : col_seq_lds<float>(p.log2n2);
-        max_a = std::max(max_a, static_cast<size_t>(seq ? 1 : d.nf) * (d.cols + 1) * d.n2);
+        const int row = opt.precision == OPO_F64 ? col_lds_row<double>(p.log2n2) : col_lds_row<float>(p.log2n2);
+        max_a = std::max(max_a, static_cast<size_t>(seq ? 1 : d.nf) * row * d.n2);
         max_b = std::max(max_b, static_cast<size_t>(d.rows) * d.n1);
         // shapes the kernels are instantiated for
         const int max_ln1 = opt.precision == OPO_F64 ? kMaxLog2N1<double> : kMaxLog2N1<float>;

@@ -4,12 +4,18 @@
 // The entries are chosen by timing the candidate schedules on the device
 // (paper_2410_02532_amd/tune.py, which writes schedule_table.inc); the lookup
 // itself is a plain table, so one shape always gets one schedule and results
-// do not depend on timings taken at run time. An instance is "alone" when its
-// handle holds no other; the schedules differ because an instance alone is
-// bound by the serial time of one tile, a batch by throughput.
+// do not depend on timings taken at run time. The batch entries apply to the
+// instances of a handle whose fields fill the chip (at least kBatchPoints field
+// samples in all, e.g. 2^9 instances of 2^10 points with three waves), the
+// others ("alone", one instance or a few) to the rest: a handle that small is
+// bound by the serial time of one tile, a full one by throughput (and resident
+// instances, one per CU, pay only when there are enough of them or when they
+// run beside the two-pass launches of larger ones).
 #pragma once
 
 namespace opo {
+
+constexpr long long kBatchPoints = 1LL << 20;
 
 struct Schedule {
     int col_log2;   // 0 = default split
@@ -20,7 +26,7 @@ struct ScheduleEntry {
     int f64;        // precision: 0 FP32, 1 FP64
     int nf;         // coupled waves
     int log2nt;
-    int batched;    // 0 alone, 1 in a batch
+    int batched;    // 0 alone (a handle below kBatchPoints), 1 in a batch
     Schedule s;
 };
 

@@ -170,10 +170,12 @@ template <typename R> __host__ __device__ constexpr int col_cols(int ln2)
     return kThreads * col_pf<R>(ln2) >> ln2;
 }
 // LDS layout of a column tile: position p of column c of field f at element
-// f*(COLS + 1)*n2 + p*(COLS + 1) + c. The spare element per row of COLS shifts
-// consecutive positions by one element across the banks, and every offset
+// f*ROW*n2 + p*ROW + c with ROW = COLS + OPO_COL_PAD, so that every offset
 // between a thread's positions is a compile-time constant.
-template <typename R> __host__ __device__ constexpr int col_lds_row(int ln2) { return col_cols<R>(ln2) + 1; }
+#ifndef OPO_COL_PAD
+#define OPO_COL_PAD 1
+#endif
+template <typename R> __host__ __device__ constexpr int col_lds_row(int ln2) { return col_cols<R>(ln2) + OPO_COL_PAD; }
 // Column tiles whose fields would need more than 32 KB of LDS for one
 // exchange pass their fields through it one at a time (a single field's
 // worth of LDS), so that several workgroups still fit a CU.
@@ -481,7 +483,7 @@ __device__ __forceinline__ void column_fft(cplx<R> (&v)[NF][PF], cplx<R> *s, con
                                            const Phasor<R> *__restrict__ tw)
 {
     constexpr int N = 1 << LN2;
-    constexpr int ROW = COLS + 1;   // col_lds_row
+    constexpr int ROW = col_lds_row<R>(LN2);
     if constexpr (N > 1 && col_seq_lds<R>(LN2)) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -560,7 +562,7 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     int base[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f)
-        base[f] = f * (COLS + 1) * N + c;
+        base[f] = f * col_lds_row<R>(LN2) * N + c;
     if (flags & A_INV) {
         if constexpr (N > 1) {
 #pragma unroll

@@ -226,9 +226,10 @@ def test_resident_beside_two_pass_equals_singles(precision):
 
 
 def test_resident_profile_counts_and_auto_schedule():
-    """The profile option times the resident launches as their own class (one per shape and
-    round trip); the automatic schedule runs a batch's 2^10..2^12 instances resident and an
-    instance alone in two passes."""
+    """The profile option times the resident launches as their own class (one timed group
+    per round trip); the automatic schedule runs the 2^10..2^12 instances of a handle that
+    fills the chip (2^20 samples or more) resident, and those of a small handle, or of an
+    instance alone, in two passes."""
     insts = _mixed_batch()
     with B.Opo(insts, 6, precision="f32", schedule="resident", profile=True) as h:
         h.cavity_roundtrip(2)
@@ -236,9 +237,15 @@ def test_resident_profile_counts_and_auto_schedule():
     # one timed group of resident launches per round trip (shapes (log2 nt, nf) served:
     # (12, 3), (11, 3), (10, 3), (12, 2), (10, 2))
     assert n["resident_pass"] == 2, n
-    with B.Opo(insts, 6, precision="f32", profile=True) as h:
+    with B.Opo(insts, 6, precision="f32", profile=True) as h:      # 121856 samples: small
         h.cavity_roundtrip(1)
-        assert _launches(h)["resident_pass"] > 0
+        n = _launches(h)
+        assert n["resident_pass"] == 0 and not any(h.plan(i)[2] for i in range(len(insts))), n
+    w = W.config("small_sweep", nz=6)                                # 256 instances, 1.8e6 samples
+    with B.from_workload(w, profile=True) as h:
+        h.cavity_roundtrip(1)
+        assert _launches(h)["resident_pass"] == 1
+        assert all(h.plan(i)[2] for i in range(len(w["instances"])))
     with B.Opo([insts[0]], 6, precision="f32", profile=True) as h:
         h.cavity_roundtrip(1)
         n = _launches(h)
