@@ -1000,7 +1000,13 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
     // ---- workgroup -> tile maps of the mixed launches. Workgroup b runs on
     // XCD b mod 8; row tile t of an instance goes to XCD t mod 8, column
     // tiles are spread evenly, and within an XCD the two kinds alternate in
-    // proportion to their counts
+    // proportion to their counts, the longer rows first
+    // Measured orders (MI355X, ms per round trip): the kinds interleaved in
+    // proportion to their counts with the longer rows first in each XCD (below)
+    // ran the batched sweep 0.7 % faster than unsorted; all row tiles first ran
+    // a batch of 2^16 instances 7 % and the two-wave sweep 6 % faster but the
+    // batched sweep 1 % and batches of 2^13..2^15 2-3 % slower; column tiles
+    // first was slower on the batched sweep too.
     std::vector<int> maps[2];
     if (h->mixed) {
         constexpr int kXcd = 8;
@@ -1013,6 +1019,11 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
                 const int local = tile - h->inst[tile_b_inst[tile]].tile_b0;
                 qr[local % kXcd].push_back(tile);
             }
+            // longer rows first within each XCD (stable: tile order otherwise)
+            for (int x = 0; x < kXcd; ++x)
+                std::stable_sort(qr[x].begin(), qr[x].end(), [&](int p, int q) {
+                    return h->inst[tile_b_inst[p]].log2n1 > h->inst[tile_b_inst[q]].log2n1;
+                });
             size_t len = 0;
             for (int x = 0; x < kXcd; ++x) len = std::max(len, qc[x].size() + qr[x].size());
             maps[ch].assign(len * kXcd, kNoTile);

@@ -77,3 +77,18 @@ def test_split_bad_values():
         with pytest.raises(B.OpoError) as e:
             B.Opo([ins], 10, col_log2=col)
         assert e.value.code == B.OPO_EINVAL
+
+
+def test_tuner_split_model_matches_the_library():
+    """The schedule tuner labels and deduplicates its candidates with the split it expects
+    the library's plan to give for each col_log2 option (and for the default); that model
+    must be the library's own (opo_get_plan)."""
+    from paper_2410_02532_amd import tune
+    for prec in ("f32", "f64"):
+        for l in (10, 11, 13, 14, 17, tune.MAX_LOG2[prec]):
+            ins = dict(crystal=W.crystal(1 << l), cavity=W.cavity(), fields=W.initial_fields(1 << l, 1e6, 1),
+                       pump_in=np.full(1 << l, 1e6 + 0j))
+            for cl in (0, 4, 5, 6, 7, 8):
+                with B.Opo([ins], 2, precision=prec, col_log2=cl, schedule="two_pass") as h:
+                    l1, l2, res = h.plan(0)
+                assert (l1 + l2, l2, res) == (l, tune.split_of(l, prec, cl), False), (prec, l, cl)
