@@ -147,6 +147,16 @@ __device__ __forceinline__ void lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// The same for an exchange among the lanes of one wavefront (every transform of
+// the exchange lies within one wave): LDS accesses of one wave complete in
+// order, so only code motion has to be stopped, no barrier is needed.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 // R-point DFT in registers, y_k = sum_j x_j e^{DIR 2 pi i jk/R}.
 template <int DIR, typename V> __device__ __forceinline__ void dft2(V *x)
 {
@@ -257,7 +267,7 @@ template <int N, int PF, int P, int R16 = 2048> __host__ __device__ constexpr in
 // One stage over NTR transforms held by this thread. Position n of transform
 // tr lives at LDS element base[tr] + n*LS; t is the thread's index in its
 // transform.
-template <typename R, int N, int PF, int NTR, int DIR, int LS, int RS, int P, bool LIN>
+template <typename R, int N, int PF, int NTR, int DIR, int LS, int RS, int P, bool LIN, bool WAVE>
 __device__ __forceinline__ void reg_stage(cplx<R> (&v)[NTR][PF], cplx<R> *lds, const int (&base)[NTR],
                                           int t, const Phasor<R> *__restrict__ tw)
 {
@@ -309,24 +319,24 @@ __device__ __forceinline__ void reg_stage(cplx<R> (&v)[NTR][PF], cplx<R> *lds, c
         }
     }
     if constexpr (!LAST) {
-        lds_sync();
+        if constexpr (WAVE) wave_lds_sync(); else lds_sync();
 #pragma unroll
         for (int tr = 0; tr < NTR; ++tr)
 #pragma unroll
             for (int m = 0; m < PF; ++m)
                 v[tr][m] = lds[at(base[tr] + (t + m * STRIDE) * LS)];
-        lds_sync();
+        if constexpr (WAVE) wave_lds_sync(); else lds_sync();
     }
 }
 
-template <typename R, int N, int PF, int NTR, int DIR, int LS, int P, int R16, bool LIN>
+template <typename R, int N, int PF, int NTR, int DIR, int LS, int P, int R16, bool LIN, bool WAVE>
 __device__ __forceinline__ void reg_fft_from(cplx<R> (&v)[NTR][PF], cplx<R> *lds, const int (&base)[NTR],
                                              int t, const Phasor<R> *__restrict__ tw)
 {
     if constexpr (P < N) {
         constexpr int RS = stage_radix<N, PF, P, R16>();
-        reg_stage<R, N, PF, NTR, DIR, LS, RS, P, LIN>(v, lds, base, t, tw);
-        reg_fft_from<R, N, PF, NTR, DIR, LS, P * RS, R16, LIN>(v, lds, base, t, tw);
+        reg_stage<R, N, PF, NTR, DIR, LS, RS, P, LIN, WAVE>(v, lds, base, t, tw);
+        reg_fft_from<R, N, PF, NTR, DIR, LS, P * RS, R16, LIN, WAVE>(v, lds, base, t, tw);
     }
 }
 
@@ -335,12 +345,14 @@ __device__ __forceinline__ void reg_fft_from(cplx<R> (&v)[NTR][PF], cplx<R> *lds
 // thread of the workgroup must call it (it synchronizes the workgroup when
 // N > PF). LS is the LDS element stride between consecutive positions; radix-16
 // stages serve transforms of up to R16 points. LIN: base and LS already lay the
-// positions out without bank conflicts (no lds_index padding).
-template <typename R, int N, int PF, int NTR, int DIR, int LS, int R16 = 2048, bool LIN = false>
+// positions out without bank conflicts (no lds_index padding). WAVE: the threads
+// of every transform exchanging through this thread's LDS positions belong to its
+// own wavefront, so the exchanges synchronize the wave only.
+template <typename R, int N, int PF, int NTR, int DIR, int LS, int R16 = 2048, bool LIN = false, bool WAVE = false>
 __device__ __forceinline__ void reg_fft(cplx<R> (&v)[NTR][PF], cplx<R> *lds, const int (&base)[NTR], int t,
                                         const Phasor<R> *__restrict__ tw)
 {
-    reg_fft_from<R, N, PF, NTR, DIR, LS, 1, R16, LIN>(v, lds, base, t, tw);
+    reg_fft_from<R, N, PF, NTR, DIR, LS, 1, R16, LIN, WAVE>(v, lds, base, t, tw);
 }
 
 // The same transforms stage by stage through one transform's worth of LDS:

@@ -194,6 +194,9 @@ template <typename R> __host__ __device__ constexpr bool col_seq_lds(int ln2)
 // points the tiles of four times the rows halve the workgroups of a single
 // instance, whose launches are then too few to fill the chip; in FP64 the
 // registers are better spent on occupancy.)
+#ifndef OPO_ROW_WAVE_MAX
+#define OPO_ROW_WAVE_MAX 64
+#endif
 #ifndef OPO_ROW_R16_MIN
 #define OPO_ROW_R16_MIN 4096
 #endif
@@ -729,7 +732,10 @@ __device__ __forceinline__ void row_tile(const StepArgs<R> &a, const InstDesc &d
         }
     }
     const int base[1] = {w * N};
-    reg_fft<R, N, PF, 1, -1, 1>(v, s, base, t, a.tw);
+    // a row of at most 64 threads lies within one wavefront (rows start at
+    // multiples of T), and rows occupy disjoint LDS
+    constexpr bool WAVE = T <= OPO_ROW_WAVE_MAX;
+    reg_fft<R, N, PF, 1, -1, 1, 2048, false, WAVE>(v, s, base, t, a.tw);
 
     if (!(flags & B_FWD_ONLY)) {
         if (pre) {
@@ -762,7 +768,7 @@ __device__ __forceinline__ void row_tile(const StepArgs<R> &a, const InstDesc &d
                     v[0][m] = cscale(v[0][m], static_cast<R>(inv_nt));
             }
         }
-        reg_fft<R, N, PF, 1, +1, 1>(v, s, base, t, a.tw);
+        reg_fft<R, N, PF, 1, +1, 1, 2048, false, WAVE>(v, s, base, t, a.tw);
     }
     if (act && !stopped)
 #pragma unroll
