@@ -13,7 +13,7 @@ from paper_2410_02532_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 TOL_E = {"f64": 1e-10, "f32": 1e-3}
-TOL = {"f64": 1e-10, "f32": 1e-3}
+TOL = {"f64": 1e-11, "f32": 1e-4}
 
 
 def say(*a):
@@ -87,4 +87,4 @@ def test_cascade_batch_equals_singles_and_oracle():
                                                 ins["pump_in"], nrt, record=True)
         for x in range(3):
             assert np.max(np.abs(batch[i][1][:, x] - e_ref[:, x]) / e_ref[:, x]) <= 1e-3
-            assert rel_l2(batch[i][2][x], rec[-1, x]) <= 1e-3
+            assert rel_l2(batch[i][2][x], rec[-1, x]) <= 1e-4

@@ -69,7 +69,7 @@ def test_fourth_order_round_trips_batch():
         ref, e_ref = oracle.roundtrips(dict(ins["crystal"], order=4), ins["cavity"], ins["fields"],
                                        ins["pump_in"], nz, nrt)
         for x in range(3):
-            assert rel_l2(batch[i][0][x], ref[x]) <= 1e-3, (i, x)
+            assert rel_l2(batch[i][0][x], ref[x]) <= 1e-4, (i, x)
             assert np.max(np.abs(batch[i][1][:, x] - e_ref[:, x]) / e_ref[:, x]) <= 1e-3
 
 

@@ -1,10 +1,12 @@
 """Parity of the gfx950 HIP path (through the C ABI) with the FP64 CPU oracle.
 
 Both sides receive the same seeded inputs from the workloads module. Bars:
-complex128 runs match the oracle to 1e-11 relative L2 per field and pass;
-complex64 runs (FP64 phase arguments and energies) to 1e-4 relative L2 per
-field and pass, and 1e-3 in round-trip energies, as the target of the method's
-FP32 path states. Bit-exact equalities hold where the same kernels run on
+complex128 runs match the oracle to 1e-11 relative L2 per field; complex64 runs
+(FP64 phase arguments and energies) to 1e-4 relative L2 per field, and 1e-3 in
+round-trip energies, as the target of the method's FP32 path states. The field
+bars hold for one pass and for runs of round trips alike: the largest error
+measured after 40 round trips of the SRO is 8e-6 (complex64) and 2e-13
+(complex128), a twelfth and a fiftieth of the bar. Bit-exact equalities hold where the same kernels run on
 the same data (batch vs single, graph vs plain launches, repeated runs, a pass
 split in two calls).
 """
@@ -125,7 +127,7 @@ def test_roundtrip_parity_sro(precision):
     assert e.shape == (nrt, 3)
     for x in range(3):
         assert np.max(np.abs(e[:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E[precision]
-        assert rel_l2(got[x], ref[x]) <= 10 * TOL[precision]
+        assert rel_l2(got[x], ref[x]) <= TOL[precision]
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
@@ -144,7 +146,7 @@ def test_roundtrip_parity_gdd_eom_pulsed(precision):
         got = h.get_fields()
     for x in range(3):
         assert np.max(np.abs(e[:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E[precision]
-        assert rel_l2(got[x], ref[x]) <= 10 * TOL[precision], (x, rel_l2(got[x], ref[x]))
+        assert rel_l2(got[x], ref[x]) <= TOL[precision], (x, rel_l2(got[x], ref[x]))
 
 
 def test_batch_of_uneven_sizes_equals_singles_and_oracle():
@@ -170,7 +172,7 @@ def test_batch_of_uneven_sizes_equals_singles_and_oracle():
         ref, e_ref = oracle.roundtrips(ins["crystal"], ins["cavity"], ins["fields"], ins["pump_in"],
                                        nz, nrt)
         for x in range(3):
-            assert rel_l2(batch[i][0][x], ref[x]) <= 10 * TOL["f32"], (i, x)
+            assert rel_l2(batch[i][0][x], ref[x]) <= TOL["f32"], (i, x)
 
 
 def test_graph_replay_equals_plain_launches_and_is_deterministic():
@@ -227,7 +229,7 @@ def test_full_size_sro_bench_configuration():
         got = h.get_fields()
     for x in range(3):
         assert np.max(np.abs(e[:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E["f32"]
-        assert rel_l2(got[x], ref[x]) <= 10 * TOL["f32"], (x, rel_l2(got[x], ref[x]))
+        assert rel_l2(got[x], ref[x]) <= TOL["f32"], (x, rel_l2(got[x], ref[x]))
 
 
 def test_mixed_schedule_batch_equals_singles_and_oracle():
@@ -257,7 +259,7 @@ def test_mixed_schedule_batch_equals_singles_and_oracle():
             assert np.array_equal(prop[i], h.get_fields())
         ref, e_ref = oracle.roundtrips(ins["crystal"], ins["cavity"], ins["fields"], ins["pump_in"], nz, nrt)
         for x in range(3):
-            assert rel_l2(batch[i][0][x], ref[x]) <= 10 * TOL["f32"], (i, x)
+            assert rel_l2(batch[i][0][x], ref[x]) <= TOL["f32"], (i, x)
             assert np.max(np.abs(batch[i][1][:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E["f32"]
 
 
@@ -285,7 +287,7 @@ def test_mixed_schedule_with_gdd_and_eom():
             assert np.array_equal(batch[i][1], h.energy_history())
         ref, e_ref = oracle.roundtrips(ins["crystal"], ins["cavity"], ins["fields"], ins["pump_in"], nz, nrt)
         for x in range(3):
-            assert rel_l2(batch[i][0][x], ref[x]) <= 10 * TOL["f32"], (i, x)
+            assert rel_l2(batch[i][0][x], ref[x]) <= TOL["f32"], (i, x)
             assert np.max(np.abs(batch[i][1][:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E["f32"]
 
 
@@ -309,7 +311,7 @@ def test_fp64_mixed_schedule_batch():
             assert np.array_equal(batch[i][1], h.energy_history())
         ref, e_ref = oracle.roundtrips(ins["crystal"], ins["cavity"], ins["fields"], ins["pump_in"], nz, nrt)
         for x in range(3):
-            assert rel_l2(batch[i][0][x], ref[x]) <= 10 * TOL["f64"], (i, x)
+            assert rel_l2(batch[i][0][x], ref[x]) <= TOL["f64"], (i, x)
             assert np.max(np.abs(batch[i][1][:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E["f64"]
 
 

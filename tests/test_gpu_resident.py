@@ -2,7 +2,7 @@
 its round-trip boundary) against the FP64 oracle, through the C ABI.
 
 Bars as for the two-pass kernels: complex128 to 1e-11 relative L2 per field and
-pass, complex64 to 1e-4 per pass and 1e-3 in round-trip energies. Exact
+pass or run of round trips, complex64 to 1e-4 and 1e-3 in round-trip energies. Exact
 equalities hold where the same kernels run on the same data: a resident instance
 in a batch (beside two-pass instances) equals its own single run, graph replay
 equals plain launches, and the adaptive step and the spectrum read-out (which run
@@ -97,7 +97,7 @@ def test_resident_round_trips_gdd_eom_pulsed(precision):
         got = h.get_fields()
     for x in range(3):
         assert np.max(np.abs(e[:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E[precision], x
-        assert rel_l2(got[x], ref[x]) <= 10 * TOL[precision], (x, rel_l2(got[x], ref[x]))
+        assert rel_l2(got[x], ref[x]) <= TOL[precision], (x, rel_l2(got[x], ref[x]))
 
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
@@ -221,7 +221,7 @@ def test_resident_beside_two_pass_equals_singles(precision):
         ref, e_ref = oracle.roundtrips(ins["crystal"], ins["cavity"], ins["fields"], ins["pump_in"], nz, nrt)
         nf = ref.shape[0]
         for x in range(nf):
-            assert rel_l2(batch[i][0][x], ref[x]) <= 10 * TOL[precision], (i, x)
+            assert rel_l2(batch[i][0][x], ref[x]) <= TOL[precision], (i, x)
             assert np.max(np.abs(batch[i][1][:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E[precision], (i, x)
 
 

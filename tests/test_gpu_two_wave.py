@@ -1,7 +1,7 @@
 """Parity of the HIP path's two-wave (degenerate) model with the FP64 oracle.
 
 Same bars as the three-wave path: complex128 to 1e-11 relative L2 per field and
-pass, complex64 to 1e-4 per pass and 1e-3 in round-trip energies. Two-wave
+pass or run of round trips, complex64 to 1e-4 and 1e-3 in round-trip energies. Two-wave
 instances share launches with three-wave ones; each instance of such a batch
 equals its own single-instance run bit for bit.
 """
@@ -108,7 +108,7 @@ def test_two_and_three_wave_instances_share_a_batch():
             assert np.array_equal(batch[i][1], h.energy_history())
         ref, e_ref = oracle.roundtrips(ins["crystal"], ins["cavity"], ins["fields"], ins["pump_in"], nz, nrt)
         for x in range(nf):
-            assert rel_l2(batch[i][0][x], ref[x]) <= 10 * TOL["f32"], (i, x)
+            assert rel_l2(batch[i][0][x], ref[x]) <= TOL["f32"], (i, x)
             assert np.max(np.abs(batch[i][1][:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E["f32"]
 
 
@@ -127,7 +127,7 @@ def test_two_wave_gdd_eom_and_spectrum(precision):
         spec = h.get_fields(domain=1)
     for x in range(2):
         assert np.max(np.abs(e[:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E[precision]
-        assert rel_l2(got[x], ref[x]) <= 10 * TOL[precision], (x, rel_l2(got[x], ref[x]))
+        assert rel_l2(got[x], ref[x]) <= TOL[precision], (x, rel_l2(got[x], ref[x]))
         assert rel_l2(spec[x], np.fft.fft(got[x])) <= (1e-13 if precision == "f64" else 1e-6)
 
 
