@@ -434,6 +434,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="batched_sweep")
     ap.add_argument("--precision", default="f32", choices=("f32", "f64"))
+    ap.add_argument("--count", type=int, default=None,
+                    help="instances of a batched workload other than its default (same recipe)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the variants (FP64, single instance, other workloads)")
@@ -461,17 +463,18 @@ def main():
         return 0
 
     name = args.workload
-    w = W.config(name, precision=args.precision) if name == "sro_cw" else W.config(name)
+    over = {} if args.count is None else dict(count=args.count)
+    w = W.config(name, precision=args.precision, **over) if name == "sro_cw" else W.config(name, **over)
     steps = args.steps if args.steps is not None else w["n_rt"]
     errors = not args.no_errors
     variants = not args.no_variants
     _, nproc = host_info()
     jobs = OracleJobs(max(1, min(8, (nproc or 2) - 2)) if errors else 0)
-    sweep = name == "batched_sweep"
+    sweep = name == "batched_sweep" and not over     # the stored long runs are of the default batch
     head_picks = picks_per_size(w, by_level=True) if sweep else [0]
     if errors:
         for i in head_picks:
-            jobs.submit(("head", i), ("pass", name, {}, i, None))
+            jobs.submit(("head", i), ("pass", name, over, i, None))
         if variants:
             jobs.submit("sro_pass", ("pass", "sro_cw", {}, 0, None))
             jobs.submit("sync_pass", ("pass", "sync_pumped", dict(nt=1 << 18), 0, None))
@@ -516,6 +519,8 @@ def main():
     }
     if not args.no_roofline:
         line["roofline"] = roofline(w, args.precision, min(steps, 100), graph_rt_s=dev_s / steps)
+        if over:
+            line["roofline"]["traffic"] = None   # the counter runs cover the default batch only
         print("roofline: %s" % json.dumps(line["roofline"]), file=sys.stderr, flush=True)
 
     var = {}
