@@ -61,6 +61,20 @@ def build(verbose=False, sanitize=False, jobs=None):
     return out
 
 
+def build_microbench(verbose=False):
+    """Compile the stand-alone microbenchmarks (microbench/*.hip) as a build check; the
+    executables go to a temporary directory (run them with the commands in their headers)."""
+    mb = os.path.join(PKG, "microbench")
+    with tempfile.TemporaryDirectory(prefix="opo_mb_") as tmpd:
+        for f in sorted(os.listdir(mb)):
+            if f.endswith(".hip"):
+                cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
+                       "-packed-fp32-ops", os.path.join(mb, f), "-o", os.path.join(tmpd, f[:-4])]
+                if verbose:
+                    print(" ".join(cmd), flush=True)
+                subprocess.check_call(cmd)
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--sanitize", action="store_true")
