@@ -84,7 +84,21 @@ struct Group {
     int count;    // tiles
     int half;     // half of the batch (mixed schedule), 0 otherwise
     int nf;       // coupled waves of the group's instances (column groups)
+    int only = 0; // 1 + the instance of every tile of the group, or 0
 };
+
+// StepArgs::inst_only of every group: whether all its tiles belong to one instance.
+static void set_only(std::vector<Group> &groups, const std::vector<int> &tile_inst)
+{
+    for (Group &g : groups) {
+        g.only = 0;
+        if (g.count < 1) continue;
+        const int first = tile_inst[g.tile0];
+        bool one = true;
+        for (int t = g.tile0; t < g.tile0 + g.count && one; ++t) one = tile_inst[t] == first;
+        if (one) g.only = first + 1;
+    }
+}
 
 // Index of the size range (kColRanges / kRowRanges) that contains ln.
 template <size_t K> static int range_of(const int (&ranges)[K][2], int ln)
@@ -603,6 +617,7 @@ static hipError_t launch_a(opo_t *h, StepArgs<R> a, int flags, int step, int hal
             if (half >= 0 && g.half != half) continue;
             a.tile0 = g.tile0;
             a.tile_count = g.count;
+            a.inst_only = g.only;
             void *args[] = {&a};
             HIP_RET(hipLaunchKernel(column_fn<R>(g.ln, g.nf), dim3(g.count), dim3(kThreads), args, h->lds_a,
                                     h->stream));
@@ -623,6 +638,7 @@ static hipError_t launch_b(opo_t *h, StepArgs<R> a, int flags, int step = 0, int
         for (const Group &g : set ? h->res_groups_b : h->groups_b) {
             a.tile0 = g.tile0;
             a.tile_count = g.count;
+            a.inst_only = g.only;
             void *args[] = {&a};
             HIP_RET(hipLaunchKernel(row_fn<R>(g.ln), dim3(g.count), dim3(kThreads), args, h->lds_b, h->stream));
         }
@@ -984,6 +1000,10 @@ static int init_impl(opo_t **out, int n, const opo_fields_t *f, const opo_crysta
         }
     if (static_cast<int>(tile_a_inst.size()) != h->tiles_a || static_cast<int>(tile_b_inst.size()) != h->tiles_b)
         return bail(fail(OPO_EINVAL, "internal: a transform length has no kernel"));
+    set_only(h->groups_a, tile_a_inst);
+    set_only(h->groups_b, tile_b_inst);
+    set_only(h->res_groups_a, tile_a_inst);
+    set_only(h->res_groups_b, tile_b_inst);
     if (n >= 2 && h->groups_a.size() == 2 && h->groups_b.size() == 2 &&
         h->groups_a[0].half == 0 && h->groups_a[1].half == 1 && h->groups_b[0].half == 0 &&
         h->groups_b[1].half == 1) {

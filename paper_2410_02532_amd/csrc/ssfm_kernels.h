@@ -104,6 +104,8 @@ struct AdaptState {
 template <typename R> struct StepArgs {
     const InstDesc *inst;
     const int *tile_inst;     // tile -> instance
+    int inst_only;            // 1 + the instance of every tile of the launch, or 0 (tiles
+                              // of several instances: look each up in tile_inst)
     cplx<R> *state;
     const cplx<R> *pump;
     const Phasor<R> *tw;      // butterfly twiddles e^{-2 pi i q/kTwL}
@@ -532,7 +534,7 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
     double dz = a.dz_arg > 0.0 ? a.dz_arg : d.length_mm / a.nz;
     double zb = a.dz_arg > 0.0 ? a.zbase : 0.0;
     if (a.adapt) {
-        const AdaptState &st = a.adapt[a.tile_inst[tile]];
+        const AdaptState &st = a.adapt[a.inst_only > 0 ? a.inst_only - 1 : a.tile_inst[tile]];
         dz = st.dz * a.adapt_scale;
         zb = st.z;
     }
@@ -683,9 +685,10 @@ __global__ __launch_bounds__(kThreads) void column_pass(StepArgs<R> a)
     __shared__ Coupling<R> cpl;
     __shared__ double red[3 * kThreads / 64];
     const int tile = a.tile0 + blockIdx.x;
-    if (a.adapt && a.adapt[a.tile_inst[tile]].status != 0) return;
-    column_dispatch<R, LO, HI, NF>(a, a.inst[a.tile_inst[tile]], tile, reinterpret_cast<cplx<R> *>(lds_raw),
-                                   &cpl, red);
+    // a launch over one instance skips the dependent load of the tile's instance
+    const int ii = a.inst_only > 0 ? a.inst_only - 1 : a.tile_inst[tile];
+    if (a.adapt && a.adapt[ii].status != 0) return;
+    column_dispatch<R, LO, HI, NF>(a, a.inst[ii], tile, reinterpret_cast<cplx<R> *>(lds_raw), &cpl, red);
 }
 
 // ------------------------------------------------------------------------
@@ -789,8 +792,9 @@ __global__ __launch_bounds__(kThreads) void row_pass(StepArgs<R> a)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     const int tile = a.tile0 + blockIdx.x;
-    if (a.adapt && a.adapt[a.tile_inst[tile]].status != 0) return;
-    row_dispatch<R, LO, HI, true>(a, a.inst[a.tile_inst[tile]], tile, reinterpret_cast<cplx<R> *>(lds_raw));
+    const int ii = a.inst_only > 0 ? a.inst_only - 1 : a.tile_inst[tile];   // as in column_pass
+    if (a.adapt && a.adapt[ii].status != 0) return;
+    row_dispatch<R, LO, HI, true>(a, a.inst[ii], tile, reinterpret_cast<cplx<R> *>(lds_raw));
 }
 
 // Size ranges served by one launch: shapes of similar register use share a
