@@ -538,9 +538,6 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
         dz = st.dz * a.adapt_scale;
         zb = st.z;
     }
-    if (flags & (A_RK_PREV | A_RK_THIS))
-        coupling_tile<R>(d, zb + a.zf_prev * dz, a.hf_prev * dz, zb + a.zf_this * dz, a.hf_this * dz, cpl);
-
     V v[NF][PF];
     // four-step twiddle W_nt^{j1 k2} of sample m, read from the table of this
     // (nt, n1) where it is used (before the inverse and after the forward
@@ -563,6 +560,11 @@ __device__ __forceinline__ void column_tile(const StepArgs<R> &a, const InstDesc
             for (int m = 0; m < PF; ++m)
                 el32(sp, q0 + m * cstep + f * nt) = v[f][m];
     }
+
+    // the FP64 phasors of the RK4 couplings, formed by six threads once the field
+    // loads are in flight (their latency then covers it)
+    if (flags & (A_RK_PREV | A_RK_THIS))
+        coupling_tile<R>(d, zb + a.zf_prev * dz, a.hf_prev * dz, zb + a.zf_this * dz, a.hf_this * dz, cpl);
 
     int base[NF];
 #pragma unroll
