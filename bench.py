@@ -384,6 +384,53 @@ def cpu_baseline(w, budget_s=12.0, max_rt=60, pool_budget_s=10.0, max_workers=16
     return out
 
 
+def cpu_configs(budget_s=8.0):
+    """The FP64 oracle per core on every configuration (bounded samples; the cost of a
+    fixed step, and so of a round trip, does not change along a run): c0 a whole pass, c1
+    and c2 round trips from their seeded inputs for about budget_s each, c3 the benchmark's
+    own cpu_baseline sample (one core and all cores), c4 a partial pass of one instance
+    (20 of its 200 steps; the boundary adds one step's worth of pointwise work per round
+    trip)."""
+    import oracle
+    out = {}
+
+    def rts(name, over, label):
+        w = W.config(name, **over)
+        a, n, t = w["fields"], 0, 0.0
+        while n < 1 or (t < budget_s and n < 2000):
+            t0 = time.perf_counter()
+            a, _ = oracle.roundtrips(w["crystal"], w["cavity"], a, w["pump_in"], w["nz"], 1)
+            t += time.perf_counter() - t0
+            n += 1
+        nt = w["crystal"]["nt"]
+        out[label] = {"value": nt * w["nz"] * n / t, "unit": "field-point-steps/s", "cores": 1,
+                      "sample": "%d round trip(s) of Nt = %d, Nz = %d from the seeded input, %.1f s"
+                                % (n, nt, w["nz"], t)}
+
+    w = W.config("single_pass")
+    cr = w["crystal"]
+    t0 = time.perf_counter()
+    oracle.ssfm_pass(cr, w["fields"], w["nz"], cr["length_mm"] / w["nz"])
+    t = time.perf_counter() - t0
+    out["c0_single_pass_2^10"] = {"value": cr["nt"] * w["nz"] / t, "unit": "field-point-steps/s", "cores": 1,
+                                  "sample": "the whole pass (Nz = %d), %.2f s" % (w["nz"], t)}
+    rts("sro_cw", {}, "c1_sro_cw_2^14")
+    for l in (16, 17, 18):
+        rts("sync_pumped", dict(nt=1 << l), "c2_sync_pumped_2^%d" % l)
+    out["c3_batched_sweep"] = cpu_baseline(W.config("batched_sweep"))
+    w = W.config("dro_large")
+    ins = w["instances"][0]
+    cr = ins["crystal"]
+    k = 20
+    t0 = time.perf_counter()
+    oracle.ssfm_pass(cr, ins["fields"], k, cr["length_mm"] / w["nz"])
+    t = time.perf_counter() - t0
+    out["c4_dro_large_2^20"] = {"value": cr["nt"] * k / t, "unit": "field-point-steps/s", "cores": 1,
+                                "sample": "%d of the %d steps of one instance's pass, %.1f s" % (k, w["nz"], t)}
+    model, nproc = host_info()
+    return {"oracle_per_config": out, "kind": "oracle", "host": model, "nproc": nproc}
+
+
 def copy_calibration(nbytes=256 << 20):
     """A plain device copy of known size, for scaling HBM counters."""
     import torch
@@ -442,10 +489,15 @@ def main():
     ap.add_argument("--no-errors", action="store_true", help="skip the errors against the oracle")
     ap.add_argument("--no-roofline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--cpu-configs", action="store_true",
+                    help="only the oracle's per-core rate on every configuration (no GPU), one JSON line")
     ap.add_argument("--adaptive-only", action="store_true",
                     help="only the adaptive-step variant (adaptive_pulsed), one JSON line")
     args = ap.parse_args()
 
+    if args.cpu_configs:
+        print(json.dumps(cpu_configs()), flush=True)
+        return 0
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the path has no multi-GPU mode "
               "(batches shard by instance with no communication; see the design notes)",
