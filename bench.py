@@ -743,9 +743,15 @@ def main():
         print("errors vs oracle: %.1f s after the GPU work" % (time.perf_counter() - t0), file=sys.stderr,
               flush=True)
     jobs.close()
-    for v in var.values():
+    for name_v, v in var.items():
         for k in [k for k in v if k.startswith("_")]:
             del v[k]
+        # whole-run rate against the HBM roofline at the algorithmic bytes of one read and
+        # one write of every field per z-step (resident instances can exceed 1)
+        if v.get("unit", "field-point-steps/s") == "field-point-steps/s":
+            nf = 2 if "degenerate" in name_v else 3
+            bpu = nf * 2 * (16 if name_v.startswith("f64") else 8)
+            v["hbm_frac_algorithmic"] = round(v["value"] * bpu / (HBM_PEAK_GBS * 1e9), 5)
     if var:
         line["variants"] = var
         print("variants: %s" % json.dumps(var), file=sys.stderr, flush=True)
