@@ -180,7 +180,8 @@ template <typename R> static const void *resident_fn(int ln, int nf)
 }
 static int resident_threads(int ln, int precision)
 {
-    return (1 << ln) / (precision == OPO_F64 ? res_pf<double, 10>() : res_pf<float, 10>());
+    if (precision == OPO_F64) return ln <= 10 ? res_threads<double, 10>() : res_threads<double, 11>();
+    return ln <= 10 ? res_threads<float, 10>() : ln == 11 ? res_threads<float, 11>() : res_threads<float, 12>();
 }
 static bool resident_shape(int ln, int precision)
 {

@@ -851,19 +851,27 @@ __global__ __launch_bounds__(kThreads, (mixed_min_blocks<R, CR, RR>())) void mix
 // Resident pass: one workgroup holds one instance of nt = 2^LN points for a
 // whole crystal pass, and in a round trip also the boundary on both sides, so
 // the fields cross HBM once per pass instead of twice per z-step. Thread t
-// keeps samples t + m*T (m < 16, T = nt/16) of every field in registers: the
+// keeps samples t + m*T (m < PF, T = nt/PF) of every field in registers: the
 // RK4 half-steps find the NF fields of a time point in one thread, and the
-// full-length transforms of one field at a time (radix-16 Stockham stages with
-// LDS exchanges, fft_tile.h) return the bins in natural order to the same
+// full-length transforms of one field at a time (Stockham stages with LDS
+// exchanges, fft_tile.h) return the bins in natural order to the same
 // positions, where the natural-order propagator table H_x(k)/nt applies.
-// Shapes: FP32 nt 2^10..2^12 with 16 samples of each field per thread
-// (radix-16 stages), FP64 2^10..2^11 with 8 (radix 8), on nt/PF threads: the
-// registers of one wave per SIMD then hold the fields, a stage's twiddles and
-// the RK4 without spills. (FP32 2^13 spilled with 512 threads of 16 samples
-// and with 1024 of 8; FP64 with 16 samples.)
+// Shapes: FP32 nt 2^10..2^12 and FP64 2^10..2^11. Samples per thread and
+// field (res_pf): 8 (radix-8 stages; FP64 2^10: 4), so that an instance runs
+// on nt/8 threads, two waves per SIMD at 2^12, with the fields, a stage's
+// twiddles and the RK4 in registers without spills. With 16 samples (radix
+// 16, half the threads, one wave per SIMD) the launches waited on latency: a
+// batch of 2^12 instances ran at 3.8e10 field-point-steps/s against 5.6e10
+// with 8. With 4, FP32 2^12 (1024 threads, four waves per SIMD) spills and
+// 2^10..2^11 gain alone but slow a mix of sizes down (more waves beside the
+// 2^12 instances); FP64 2^10 gains 5 %. FP32 2^13 spills with 512 threads of
+// 16 samples and with 1024 of 8.
 constexpr int kResMinLog2 = 10;
 template <typename R> constexpr int kResMaxLog2 = sizeof(R) == 4 ? 12 : 11;
-template <typename R, int LN> __host__ __device__ constexpr int res_pf() { return sizeof(R) == 4 ? 16 : 8; }
+template <typename R, int LN> __host__ __device__ constexpr int res_pf()
+{
+    return (sizeof(R) == 8 && LN <= 10) ? 4 : 8;
+}
 template <typename R, int LN> __host__ __device__ constexpr int res_threads() { return (1 << LN) / res_pf<R, LN>(); }
 
 // Fixed-order sum of three doubles over the W waves of a workgroup; the result
