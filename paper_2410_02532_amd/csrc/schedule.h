@@ -8,9 +8,10 @@
 // instances of a handle whose fields fill the chip (at least kBatchPoints field
 // samples in all, e.g. 2^9 instances of 2^10 points with three waves), the
 // others ("alone", one instance or a few) to the rest: a handle that small is
-// bound by the serial time of one tile, a full one by throughput (and resident
-// instances, one per CU, pay only when there are enough of them or when they
-// run beside the two-pass launches of larger ones).
+// bound by the serial time of one tile, a full one by throughput. (A resident
+// instance runs on one CU: in a batch it nearly always wins; alone only where
+// one CU's pass beats two dependent launches per z-step, e.g. the small FP64 and
+// two-wave shapes.)
 #pragma once
 
 namespace opo {

@@ -3,7 +3,7 @@ that the library's automatic schedule reads (csrc/schedule_table.inc).
 
 A key is (precision, coupled waves, log2 nt, alone or in a batch). For each key
 the candidates are the distinct four-step splits (log2 of the column length) of
-the two-pass kernels and, in a batch where the shape is served, the resident
+the two-pass kernels and, where the shape is served, the resident
 pass. Each candidate runs CW singly resonant oscillators of that shape: one
 instance alone, or a batch of same-shape instances that fills the chip (about
 2^22 points, from two to 512 instances). In a batch only splits that the default
@@ -109,7 +109,7 @@ def tune(out, summary, precisions=("f32", "f64"), nfs=(3, 2)):
                         ms = time_candidate(insts, prec, cl, "two_pass")
                         cands.append(("two-pass n2=2^%d" % n2, cl, 0, ms))
                     lo, hi = RESIDENT[prec]
-                    if batched and lo <= l <= hi:
+                    if lo <= l <= hi:
                         ms = time_candidate(insts, prec, 0, "resident")
                         cands.append(("resident", 0, 1, ms))
                     default = cands[0]

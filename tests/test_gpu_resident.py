@@ -8,6 +8,8 @@ in a batch (beside two-pass instances) equals its own single run, graph replay
 equals plain launches, and the adaptive step and the spectrum read-out (which run
 the column and row tiles of every instance) do not depend on the schedule.
 """
+import os
+import re
 import sys
 
 import numpy as np
@@ -225,11 +227,25 @@ def test_resident_beside_two_pass_equals_singles(precision):
             assert np.max(np.abs(batch[i][1][:, x] - e_ref[:, x]) / e_ref[:, x]) <= TOL_E[precision], (i, x)
 
 
+def _table():
+    """(f64, nf, log2 nt, batched) -> (col_log2, resident) from the schedule table source."""
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_2410_02532_amd", "csrc", "schedule_table.inc")
+    rows = {}
+    with open(path) as f:
+        for line in f:
+            m = re.match(r"\s*\{(\d+), (\d+), (\d+), (\d+), \{(\d+), (\d+)\}\},", line)
+            if m:
+                v = [int(x) for x in m.groups()]
+                rows[tuple(v[:4])] = (v[4], v[5])
+    return rows
+
+
 def test_resident_profile_counts_and_auto_schedule():
     """The profile option times the resident launches as their own class (one timed group
     per round trip); the automatic schedule runs the 2^10..2^12 instances of a handle that
     fills the chip (2^20 samples or more) resident, and those of a small handle, or of an
-    instance alone, in two passes."""
+    instance alone, as the table's entries for a handle below that size say."""
     insts = _mixed_batch()
     with B.Opo(insts, 6, precision="f32", schedule="resident", profile=True) as h:
         h.cavity_roundtrip(2)
@@ -237,10 +253,19 @@ def test_resident_profile_counts_and_auto_schedule():
     # one timed group of resident launches per round trip (shapes (log2 nt, nf) served:
     # (12, 3), (11, 3), (10, 3), (12, 2), (10, 2))
     assert n["resident_pass"] == 2, n
+    table = _table()
+
+    def alone(ins):   # resident under the table's entry for a handle below 2^20 samples
+        nt = ins["crystal"]["nt"]
+        nf = ins["fields"].shape[0]
+        return bool(table[(0, nf, nt.bit_length() - 1, 0)][1])
+
     with B.Opo(insts, 6, precision="f32", profile=True) as h:      # 121856 samples: small
         h.cavity_roundtrip(1)
         n = _launches(h)
-        assert n["resident_pass"] == 0 and not any(h.plan(i)[2] for i in range(len(insts))), n
+        want = [alone(ins) for ins in insts]
+        assert [h.plan(i)[2] for i in range(len(insts))] == want, want
+        assert n["resident_pass"] == (1 if any(want) else 0), n
     w = W.config("small_sweep", nz=6)                                # 256 instances, 1.8e6 samples
     with B.from_workload(w, profile=True) as h:
         h.cavity_roundtrip(1)
@@ -249,6 +274,7 @@ def test_resident_profile_counts_and_auto_schedule():
     with B.Opo([insts[0]], 6, precision="f32", profile=True) as h:
         h.cavity_roundtrip(1)
         n = _launches(h)
+        assert not alone(insts[0])            # the table keeps a 2^12 three-wave instance alone in two passes
         assert n["resident_pass"] == 0 and n["column_pass"] > 0, n
 
 
