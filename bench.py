@@ -530,6 +530,8 @@ def main():
         if variants:
             jobs.submit("sro_pass", ("pass", "sro_cw", {}, 0, None))
             jobs.submit("sync_pass", ("pass", "sync_pumped", dict(nt=1 << 18), 0, None))
+            for l in (16, 17):
+                jobs.submit(("sync_pass", l), ("pass", "sync_pumped", dict(nt=1 << l), 0, None))
             jobs.submit("sync_rt", ("rt", "sync_pumped", dict(nt=1 << 18), 0, 3))
             jobs.submit("dro_pass", ("pass", "dro_large", {}, 0, None))
             dsw = W.config("degenerate_sweep")
@@ -613,6 +615,13 @@ def main():
             d, _, hs = run_gpu(ws, n, 3, prec, keep=(0,))
             var["%s_sync_pumped_2^18" % prec] = {"value": pt_steps_per_rt(ws) * n / d, "round_trips": n,
                                                  "ms_per_step": d * 1e3 / n, "_hist": hs[0]}
+        # its smaller grids (FP32)
+        for l in (16, 17):
+            ws = W.config("sync_pumped", nt=1 << l)
+            n = 50
+            d, _, _ = run_gpu(ws, n, 3, "f32")
+            var["f32_sync_pumped_2^%d" % l] = {"value": pt_steps_per_rt(ws) * n / d, "round_trips": n,
+                                               "ms_per_step": d * 1e3 / n}
         # the large doubly resonant batch: 16 x 2^20, Nz 200, GDD and EOM
         ws = W.config("dro_large")
         n = 10
@@ -698,6 +707,10 @@ def main():
                 v["pass_rel_l2"] = rel_l2_max(gpu_pass([ws], ws["nz"], prec)[0], jobs.get("sync_pass"))
                 s, a = energy_errors(v.pop("_hist"), sync_rt, [0, 1, 2])
                 v["short_run"] = {"round_trips": 3, "signal_power_rel": s, "energy_rel_all_fields": a}
+            for l in (16, 17):
+                ws = W.config("sync_pumped", nt=1 << l)
+                var["f32_sync_pumped_2^%d" % l]["pass_rel_l2"] = rel_l2_max(
+                    gpu_pass([ws], ws["nz"], "f32")[0], jobs.get(("sync_pass", l)))
             ws = W.config("dro_large")
             v = var["f32_dro_large_16x2^20"]
             v["pass_rel_l2"] = rel_l2_max(gpu_pass([ws["instances"][0]], ws["nz"], "f32")[0], jobs.get("dro_pass"))
